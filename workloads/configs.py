@@ -1,0 +1,115 @@
+"""The wave-equation workloads as plain, seeded recipes.
+
+Each recipe fixes the mesh, the speed field, the pole count, the step tau,
+the initial states and the number of steps.  ``make`` turns a recipe into
+arrays (c^2 at every node, the residues, initial states on interior nodes).
+
+Time step for the pulse workloads (a reading; the recipes only say "tau
+spanning many wavelengths"): a Gaussian pulse of width s has its spectrum
+below k_delta = sqrt(2 ln(1/delta)) / s to relative accuracy delta; with
+the largest speed c_max its frequencies stay below Lambda = c_max k_delta,
+and tau = X / Lambda puts that band inside the interval |x| <= X on which
+the rational function matches e^{ix} (eq. RM_prop1).  tau does not change
+the cost of a step, only the shifts of the elliptic solves.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable
+
+import numpy as np
+
+from . import fields, layout
+from .rational import RationalFit, calibrated_fit
+
+DELTA = 1e-10
+
+
+@dataclasses.dataclass(frozen=True)
+class WaveRecipe:
+    name: str
+    mesh: layout.Mesh
+    speed: str                  # "smooth" | "clipped_lognormal" | "contrast4" | "const"
+    speed_seed: int
+    npoles: int
+    tau: float | None           # None: tau = X / Lambda (pulse band)
+    pulse_seeds: tuple
+    pulse_width: float
+    n_steps: int
+
+    @property
+    def nrhs(self) -> int:
+        return len(self.pulse_seeds)
+
+
+RECIPES = {
+    # 4 x 4 elements x 12^2 nodes, c = 1 + 0.25 sin sin, 21 poles, tau = 0.5
+    "wave_4x4_p12": WaveRecipe("wave_4x4_p12", layout.Mesh(4, 4, 12), "smooth",
+                               0, 21, 0.5, (0,), 0.05, 10),
+    # 32 x 32 elements x 16^2 nodes, c = clip(exp(GRF), 1, 3), 101 poles
+    "wave_32x32_p16": WaveRecipe("wave_32x32_p16", layout.Mesh(32, 32, 16),
+                                 "clipped_lognormal", 1, 101, None, (2,), 0.05, 100),
+    # 64 x 64 elements x 10^2 nodes, lognormal contrast 4, 131 poles, 32 RHS
+    "wave_64x64_p10": WaveRecipe("wave_64x64_p10", layout.Mesh(64, 64, 10),
+                                 "contrast4", 5, 131, None, tuple(range(32)), 0.05, 1000),
+}
+
+
+def speed_function(kind: str, seed: int) -> Callable:
+    if kind == "smooth":
+        return fields.smooth_speed
+    if kind == "const":
+        return lambda x, y: np.ones_like(x)
+    if kind == "clipped_lognormal":
+        return lambda x, y: fields.clipped_lognormal_speed(x, y, seed)
+    if kind == "contrast4":
+        return lambda x, y: fields.contrast_lognormal_speed(x, y, seed, 4.0)
+    raise ValueError(kind)
+
+
+def pulse_tau(fit: RationalFit, c_max: float, width: float, delta=DELTA) -> float:
+    k_delta = np.sqrt(2.0 * np.log(1.0 / delta)) / width
+    return fit.X / (c_max * k_delta)
+
+
+@dataclasses.dataclass
+class WaveInputs:
+    recipe: WaveRecipe
+    mesh: layout.Mesh
+    c2: np.ndarray              # (n_el, p*p)
+    fit: RationalFit
+    tau: float
+    u0: np.ndarray              # (nrhs, n_int)
+    v0: np.ndarray              # (nrhs, n_int)
+
+    def state(self) -> np.ndarray:
+        """[rhs][field][n_int] layout of the C-ABI."""
+        return np.ascontiguousarray(np.stack([self.u0, self.v0], axis=1))
+
+
+def make(recipe: WaveRecipe | str, n_rhs: int | None = None) -> WaveInputs:
+    if isinstance(recipe, str):
+        recipe = RECIPES[recipe]
+    mesh = recipe.mesh
+    X, Y = layout.element_nodes(mesh)
+    c = speed_function(recipe.speed, recipe.speed_seed)(X, Y)
+    c2 = np.ascontiguousarray(c * c)
+    fit = calibrated_fit(recipe.npoles)
+    tau = recipe.tau if recipe.tau is not None else pulse_tau(
+        fit, float(c.max()), recipe.pulse_width)
+    Xi, Yi = layout.interior_nodes(mesh)
+    seeds = recipe.pulse_seeds[:n_rhs] if n_rhs else recipe.pulse_seeds
+    u0 = np.stack([fields.gaussian_pulse(Xi, Yi, s, recipe.pulse_width) for s in seeds])
+    return WaveInputs(recipe, mesh, c2, fit, float(tau), u0, np.zeros_like(u0))
+
+
+def scaled(recipe: WaveRecipe | str, nex: int, ney: int, p: int | None = None,
+           npoles: int | None = None, n_steps: int | None = None) -> WaveRecipe:
+    """Same recipe on another mesh (the same field, sampled on new nodes)."""
+    if isinstance(recipe, str):
+        recipe = RECIPES[recipe]
+    m = recipe.mesh
+    return dataclasses.replace(
+        recipe, name=f"{recipe.name}@{nex}x{ney}",
+        mesh=layout.Mesh(nex, ney, p or m.p, m.x0, m.x1, m.y0, m.y1),
+        npoles=npoles or recipe.npoles, n_steps=n_steps or recipe.n_steps)
