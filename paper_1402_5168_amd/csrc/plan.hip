@@ -1,0 +1,991 @@
+// Host side of the hpsexp C-ABI: plans, merge trees, validation, arena
+// layout, the build stage (rocSOLVER / rocBLAS for the dense factorisations)
+// and the step (kernel sequence, replayed from a hipGraph).
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "hpsexp.h"
+#include "hx_kernels.h"
+
+namespace {
+
+using cd = std::complex<double>;
+using hx::BoxDesc;
+using hx::LeafDesc;
+using hx::PoleCoef;
+
+thread_local std::string g_last_error;
+
+hx_status fail(hx_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = std::string(hx_status_str(st)) + ": " + buf;
+  return st;
+}
+
+#define HIP_OK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(HX_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),   \
+                  __FILE__, __LINE__);                                                \
+  } while (0)
+
+#define RB_OK(expr)                                                                   \
+  do {                                                                                \
+    rocblas_status s_ = (expr);                                                       \
+    if (s_ != rocblas_status_success)                                                 \
+      return fail(HX_EDEVICE, "%s failed: rocblas status %d (%s:%d)", #expr, (int)s_, \
+                  __FILE__, __LINE__);                                                \
+  } while (0)
+
+#define HX_TRY(expr)                  \
+  do {                                \
+    hx_status st_ = (expr);           \
+    if (st_ != HX_OK) return st_;     \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// Chebyshev-Lobatto differentiation matrix on ascending nodes
+// x_k = -cos(k pi / N), N = p-1 (section 2.2), row-major D[i*p + j].
+std::vector<double> cheb_diff(int p) {
+  const int N = p - 1;
+  std::vector<double> D(p * p, 0.0);
+  auto c = [&](int k) { return (k == 0 || k == N) ? 2.0 : 1.0; };
+  for (int i = 0; i < p; ++i) {
+    double rowsum = 0.0;
+    for (int j = 0; j < p; ++j) {
+      if (i == j) continue;
+      // x_i - x_j = 2 sin((i+j) pi / 2N) sin((i-j) pi / 2N)
+      const double dx = 2.0 * std::sin((i + j) * M_PI / (2.0 * N)) *
+                        std::sin((i - j) * M_PI / (2.0 * N));
+      const double sgn = ((i + j) % 2) ? -1.0 : 1.0;
+      D[i * p + j] = c(i) / c(j) * sgn / dx;
+      rowsum += D[i * p + j];
+    }
+    D[i * p + i] = -rowsum;
+  }
+  return D;
+}
+
+struct Level {
+  std::vector<BoxDesc> boxes;
+  int total_ext = 0, total_n3 = 0, max_ext = 0, max_n3 = 0, max_x = 0;
+  // device offsets (bytes inside the arena)
+  size_t d_boxes = 0, d_h = 0, d_u = 0, d_g3 = 0;
+};
+
+struct Instance {
+  hx_mesh mesh{};
+  int q = 0, q2 = 0, n_leaf = 0, npole = 0, nrhs = 0, ncol = 0, M = 0;
+  double tau = 0.0, delta = 0.0, beta = 0.0;
+  std::vector<double> c2;
+  std::vector<cd> alpha, b;                 // m = -M..M
+  std::vector<LeafDesc> leaves;
+  std::vector<Level> levels;                // levels[0] = leaves (boxes empty)
+  std::vector<int> idx;
+  std::vector<PoleCoef> coef;
+  std::vector<double> nrow;
+  long long pole_stride = 0;                // complex elements per pole block
+  long long leaf_ops = 0, merge_ops = 0;    // complex elements per pole
+  double max_abs_R = 0.0, fit_X = 0.0, sum_abs_b = 0.0;
+  // arena layout (byte offsets)
+  size_t d_ops = 0, d_w = 0, d_leaves = 0, d_idx = 0, d_coef = 0, d_nrow = 0, end = 0;
+};
+
+}  // namespace
+
+struct hx_plan {
+  int device = 0;
+  unsigned flags = 0;
+  std::vector<Instance> inst;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  bool built = false;
+  // graph cache
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<double*> graph_states;
+  hipStream_t graph_stream = nullptr;
+  int* d_flag = nullptr;  // inside the arena
+  size_t d_flag_off = 0;
+};
+
+namespace {
+
+// ---- rational function checks (eqs. RM_prop1 and RM_prop2) ----------------
+
+cd R_eval(const Instance& I, double x) {
+  const cd z(0.0, x);
+  cd s = 0.0;
+  for (int k = 0; k < I.npole * 2 - 1; ++k) s += I.b[k] / (z - I.alpha[k]);
+  return s;
+}
+
+void check_fit(Instance& I) {
+  double mx = 0.0;
+  auto probe = [&](double x) { mx = std::max(mx, std::abs(R_eval(I, x))); };
+  for (int k = 0; k <= 80000; ++k) probe(-400.0 + k * 0.01);
+  for (int k = 0; k <= 4000; ++k) {
+    const double x = 400.0 * std::pow(1e7 / 400.0, k / 4000.0);
+    probe(x);
+    probe(-x);
+  }
+  I.max_abs_R = mx;
+  // largest X with |R(ix) - e^{ix}| <= delta on [-X, X] (grid step 1e-3)
+  double X = 0.0;
+  for (int k = 0;; ++k) {
+    const double x = k * 1e-3;
+    const double e1 = std::abs(R_eval(I, x) - std::exp(cd(0.0, x)));
+    const double e2 = std::abs(R_eval(I, -x) - std::exp(cd(0.0, -x)));
+    if (std::max(e1, e2) > I.delta || x > 1e5) break;
+    X = x;
+  }
+  I.fit_X = X;
+  double sb = 0.0;
+  for (auto& v : I.b) sb += std::abs(v);
+  I.sum_abs_b = sb;
+}
+
+// ---- merge tree --------------------------------------------------------------
+
+struct TBox {
+  int x0, y0, w, h;
+  std::vector<int> ext;  // global interface node ids (outer boundary pruned)
+};
+
+void build_tree(Instance& I) {
+  const int nex = I.mesh.nex, ney = I.mesh.ney, q = I.q;
+  const int n_vert = (nex - 1) * ney * q;
+  auto vnode = [&](int vx, int ey, int t) { return (vx + (nex - 1) * ey) * q + t; };
+  auto hnode = [&](int ex, int hy, int t) { return n_vert + (ex + nex * hy) * q + t; };
+  const int n_nodes = n_vert + nex * (ney - 1) * q;
+
+  std::vector<TBox> cur;
+  I.leaves.clear();
+  I.levels.clear();
+  I.levels.emplace_back();
+  long long op = 0;
+  int vec = 0;
+  for (int ey = 0; ey < ney; ++ey)
+    for (int ex = 0; ex < nex; ++ex) {
+      TBox b{ex, ey, 1, 1, {}};
+      int mask = 0;
+      if (ex > 0) { mask |= 1; for (int t = 0; t < q; ++t) b.ext.push_back(vnode(ex - 1, ey, t)); }
+      if (ex < nex - 1) { mask |= 2; for (int t = 0; t < q; ++t) b.ext.push_back(vnode(ex, ey, t)); }
+      if (ey > 0) { mask |= 4; for (int t = 0; t < q; ++t) b.ext.push_back(hnode(ex, ey - 1, t)); }
+      if (ey < ney - 1) { mask |= 8; for (int t = 0; t < q; ++t) b.ext.push_back(hnode(ex, ey, t)); }
+      LeafDesc L{};
+      L.op_off = op;
+      L.vec_off = vec;
+      L.e = (int)b.ext.size();
+      L.side_mask = mask;
+      L.elem = ex + nex * ey;
+      I.leaves.push_back(L);
+      op += align_up((size_t)I.q2 * (I.q2 + L.e), 8);
+      vec += L.e;
+      cur.push_back(std::move(b));
+    }
+  I.leaf_ops = op;
+  I.levels[0].total_ext = vec;
+  for (auto& L : I.leaves) I.levels[0].max_ext = std::max(I.levels[0].max_ext, L.e);
+
+  std::vector<int> pos(std::max(n_nodes, 1), -1);
+  int nbx = nex, nby = ney;
+  I.idx.clear();
+  while (nbx * nby > 1) {
+    const bool in_x = nbx > 1 && (cur[0].w <= cur[0].h || nby == 1);
+    const int nbx2 = in_x ? nbx / 2 : nbx, nby2 = in_x ? nby : nby / 2;
+    Level lev;
+    std::vector<TBox> next;
+    int vec_off = 0, g3_off = 0;
+    const Level& below = I.levels.back();
+    std::vector<int> below_vec;
+    if (I.levels.size() == 1)
+      for (auto& L : I.leaves) below_vec.push_back(L.vec_off);
+    else
+      for (auto& B : below.boxes) below_vec.push_back(B.vec_off);
+    for (int by = 0; by < nby2; ++by)
+      for (int bx = 0; bx < nbx2; ++bx) {
+        const int ia = in_x ? (2 * bx + nbx * by) : (bx + nbx * (2 * by));
+        const int ib = in_x ? (2 * bx + 1 + nbx * by) : (bx + nbx * (2 * by + 1));
+        const TBox& A = cur[ia];
+        const TBox& Bb = cur[ib];
+        for (size_t k = 0; k < Bb.ext.size(); ++k) pos[Bb.ext[k]] = (int)k;
+        std::vector<int> s1, s3, i1, i3a, s2, i2, i3b;
+        for (size_t k = 0; k < A.ext.size(); ++k) {
+          if (pos[A.ext[k]] >= 0) s3.push_back(A.ext[k]);
+          else { s1.push_back(A.ext[k]); i1.push_back((int)k); }
+        }
+        for (size_t k = 0; k < Bb.ext.size(); ++k) pos[Bb.ext[k]] = -1;
+        std::sort(s3.begin(), s3.end());
+        // positions of the interface nodes in a and b
+        for (size_t k = 0; k < A.ext.size(); ++k) pos[A.ext[k]] = (int)k;
+        for (int id : s3) i3a.push_back(pos[id]);
+        for (size_t k = 0; k < A.ext.size(); ++k) pos[A.ext[k]] = -1;
+        for (size_t k = 0; k < Bb.ext.size(); ++k) pos[Bb.ext[k]] = (int)k;
+        for (int id : s3) i3b.push_back(pos[id]);
+        for (size_t k = 0; k < Bb.ext.size(); ++k) pos[Bb.ext[k]] = -1;
+        for (int id : s3) pos[id] = 0;
+        for (size_t k = 0; k < Bb.ext.size(); ++k)
+          if (pos[Bb.ext[k]] < 0) { s2.push_back(Bb.ext[k]); i2.push_back((int)k); }
+        for (int id : s3) pos[id] = -1;
+
+        BoxDesc D{};
+        D.n1 = (int)s1.size();
+        D.n2 = (int)s2.size();
+        D.n3 = (int)s3.size();
+        D.a_box = ia;
+        D.b_box = ib;
+        D.a_vec = below_vec[ia];
+        D.b_vec = below_vec[ib];
+        D.vec_off = vec_off;
+        D.g3_off = g3_off;
+        D.idx_off = (int)I.idx.size();
+        I.idx.insert(I.idx.end(), i1.begin(), i1.end());
+        I.idx.insert(I.idx.end(), i2.begin(), i2.end());
+        I.idx.insert(I.idx.end(), i3a.begin(), i3a.end());
+        I.idx.insert(I.idx.end(), i3b.begin(), i3b.end());
+        const long long ext = D.n1 + D.n2;
+        D.op_off = op;
+        op += align_up((size_t)(D.n3 * (ext + D.n3) + ext * D.n3), 8);
+        vec_off += (int)ext;
+        g3_off += D.n3;
+        lev.max_ext = std::max(lev.max_ext, (int)ext);
+        lev.max_n3 = std::max(lev.max_n3, D.n3);
+        lev.max_x = std::max(lev.max_x, (int)ext + D.n3);
+        lev.boxes.push_back(D);
+
+        TBox P{A.x0, A.y0, in_x ? A.w * 2 : A.w, in_x ? A.h : A.h * 2, {}};
+        P.ext = s1;
+        P.ext.insert(P.ext.end(), s2.begin(), s2.end());
+        next.push_back(std::move(P));
+      }
+    lev.total_ext = vec_off;
+    lev.total_n3 = g3_off;
+    I.levels.push_back(std::move(lev));
+    cur.swap(next);
+    nbx = nbx2;
+    nby = nby2;
+  }
+  I.merge_ops = op - I.leaf_ops;
+  I.pole_stride = align_up((size_t)op, 16);
+}
+
+void layout_arena(hx_plan* plan) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 1));
+    return o;
+  };
+  plan->d_flag_off = take(sizeof(int));
+  for (auto& I : plan->inst) {
+    I.d_ops = take(sizeof(double2) * (size_t)I.pole_stride * I.npole);
+    I.d_w = take(sizeof(double2) * (size_t)I.ncol * I.n_leaf * I.q2);
+    for (size_t l = 0; l < I.levels.size(); ++l) {
+      Level& L = I.levels[l];
+      L.d_h = take(sizeof(double2) * (size_t)I.ncol * L.total_ext);
+      L.d_u = take(sizeof(double2) * (size_t)I.ncol * L.total_ext);
+      L.d_g3 = take(sizeof(double2) * (size_t)I.ncol * L.total_n3);
+      L.d_boxes = take(sizeof(BoxDesc) * L.boxes.size());
+    }
+    I.d_leaves = take(sizeof(LeafDesc) * I.leaves.size());
+    I.d_idx = take(sizeof(int) * I.idx.size());
+    I.d_coef = take(sizeof(PoleCoef) * I.coef.size());
+    I.d_nrow = take(sizeof(double) * I.nrow.size());
+    I.end = off;
+  }
+  plan->arena_bytes = off;
+}
+
+// Build workspace layout for a chunk of `ch` poles of one instance.
+struct WsLayout {
+  size_t A = 0, T0 = 0, T1 = 0, ipiv = 0, info = 0, ptr = 0, c2 = 0, D = 0, sigma = 0,
+         toff = 0, total = 0;
+  long long sizeA = 0, sizeT = 0, sizeIpiv = 0, sizeInfo = 0, sizePtr = 0, n_off = 0;
+};
+
+WsLayout ws_layout(const Instance& I, int ch) {
+  WsLayout w;
+  w.sizeA = (long long)I.n_leaf * I.q2 * I.q2;
+  w.sizeIpiv = (long long)I.n_leaf * I.q2;
+  w.sizeInfo = I.n_leaf;
+  long long t0 = 0;
+  for (auto& L : I.leaves) t0 += (long long)L.e * L.e;
+  w.sizeT = t0;
+  w.n_off = (long long)I.leaves.size();
+  for (size_t l = 1; l < I.levels.size(); ++l) {
+    long long m = 0, v = 0, t = 0, pv = 0;
+    for (auto& B : I.levels[l].boxes) {
+      const long long ext = B.n1 + B.n2;
+      m += (long long)B.n3 * B.n3;
+      v += ext * B.n3;
+      t += ext * ext;
+      pv += B.n3;
+    }
+    w.sizeA = std::max(w.sizeA, m + v);
+    w.sizeT = std::max(w.sizeT, t);
+    w.sizeIpiv = std::max(w.sizeIpiv, pv);
+    w.sizeInfo = std::max(w.sizeInfo, (long long)I.levels[l].boxes.size());
+    w.n_off = std::max(w.n_off, (long long)I.levels[l].boxes.size());
+  }
+  w.sizePtr = 6 * w.sizeInfo;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 1));
+    return o;
+  };
+  w.A = take(sizeof(double2) * (size_t)w.sizeA * ch);
+  w.T0 = take(sizeof(double2) * (size_t)w.sizeT * ch);
+  w.T1 = take(sizeof(double2) * (size_t)w.sizeT * ch);
+  w.ipiv = take(sizeof(int) * (size_t)w.sizeIpiv * ch);
+  w.info = take(sizeof(int) * (size_t)w.sizeInfo * ch);
+  w.ptr = take(sizeof(void*) * (size_t)w.sizePtr * ch);
+  w.c2 = take(sizeof(double) * I.c2.size());
+  w.D = take(sizeof(double) * I.mesh.p * I.mesh.p);
+  w.sigma = take(sizeof(double2) * ch);
+  w.toff = take(sizeof(long long) * 4 * (size_t)std::max<long long>(w.n_off, 1));
+  w.total = off;
+  return w;
+}
+
+// ---- validation ---------------------------------------------------------------
+
+hx_status validate_add(const hx_mesh* m, const hx_coeffs* c, double tau, double delta,
+                       const hx_rational* r, int nrhs) {
+  if (!m || !c || !r) return fail(HX_EINVAL, "null mesh, coeffs or rational");
+  if (!is_pow2(m->nex) || !is_pow2(m->ney))
+    return fail(HX_EINVAL, "nex=%d and ney=%d must be powers of two", m->nex, m->ney);
+  if (m->p < 4 || m->p > hx::kMaxP) return fail(HX_EINVAL, "p=%d outside [4, %d]", m->p, hx::kMaxP);
+  if (!(m->x1 > m->x0) || !(m->y1 > m->y0) || !std::isfinite(m->x0 + m->x1 + m->y0 + m->y1))
+    return fail(HX_EINVAL, "empty or non-finite domain");
+  if ((long long)m->nex * m->ney > (1LL << 22)) return fail(HX_EINVAL, "mesh too large");
+  if (c->kind != HX_WAVE_DIRICHLET) return fail(HX_EINVAL, "unsupported problem kind %d", c->kind);
+  if (!c->c2) return fail(HX_EINVAL, "c2 is null");
+  const long long n = (long long)m->nex * m->ney * m->p * m->p;
+  for (long long k = 0; k < n; ++k)
+    if (!(std::isfinite(c->c2[k]) && c->c2[k] > 0.0))
+      return fail(HX_EINVAL, "c2[%lld] = %g is not finite and positive", k, c->c2[k]);
+  if (!(tau > 0.0) || !std::isfinite(tau)) return fail(HX_EINVAL, "tau must be finite and > 0");
+  if (!(delta > 0.0) || !std::isfinite(delta)) return fail(HX_EINVAL, "delta must be finite and > 0");
+  if (r->npoles < 1 || r->npoles % 2 == 0 || r->npoles > 4001)
+    return fail(HX_EINVAL, "npoles=%d must be odd, 1..4001", r->npoles);
+  if (!r->alpha || !r->b) return fail(HX_EINVAL, "alpha or b is null");
+  const int M = (r->npoles - 1) / 2;
+  for (int k = 0; k < 2 * r->npoles; ++k)
+    if (!std::isfinite(r->alpha[k]) || !std::isfinite(r->b[k]))
+      return fail(HX_EINVAL, "non-finite pole or residue");
+  for (int m = 0; m <= M; ++m) {
+    const cd ap(r->alpha[2 * (M + m)], r->alpha[2 * (M + m) + 1]);
+    const cd am(r->alpha[2 * (M - m)], r->alpha[2 * (M - m) + 1]);
+    const cd bp(r->b[2 * (M + m)], r->b[2 * (M + m) + 1]);
+    const cd bm(r->b[2 * (M - m)], r->b[2 * (M - m) + 1]);
+    if (std::abs(ap - std::conj(am)) > 1e-12 * std::max(1.0, std::abs(ap)))
+      return fail(HX_EINVAL, "alpha_{-%d} != conj(alpha_%d)", m, m);
+    if (std::abs(bp - std::conj(bm)) > 1e-12 * std::max(1.0, std::abs(bp)))
+      return fail(HX_EINVAL, "b_{-%d} != conj(b_%d)", m, m);
+    if (ap.real() == 0.0) return fail(HX_EINVAL, "Re(alpha_%d) = 0 (pole on the spectrum)", m);
+  }
+  if (nrhs < 1 || nrhs > 4096) return fail(HX_EINVAL, "nrhs=%d outside [1, 4096]", nrhs);
+  return HX_OK;
+}
+
+// ---- build ---------------------------------------------------------------------
+
+struct Build {
+  hx_plan* plan;
+  rocblas_handle rb = nullptr;
+  hipStream_t s = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+};
+
+template <class T>
+T* wsp(const Build& B, size_t off) { return reinterpret_cast<T*>(B.ws + off); }
+
+// Host-to-device copy that completes before returning (the host staging
+// vectors of the build are reused right after).
+hx_status upload(const Build& B, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return HX_OK;
+  HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, B.s));
+  HIP_OK(hipStreamSynchronize(B.s));
+  return HX_OK;
+}
+
+hx_status check_info(const Build& B, const WsLayout& W, long long n, const char* what, int level) {
+  std::vector<int> info(n);
+  HIP_OK(hipMemcpyAsync(info.data(), B.ws + W.info, sizeof(int) * n, hipMemcpyDeviceToHost, B.s));
+  HIP_OK(hipStreamSynchronize(B.s));
+  for (long long k = 0; k < n; ++k)
+    if (info[k] != 0)
+      return fail(HX_ESINGULAR, "%s system %lld at level %d is singular (info %d)", what, k,
+                  level, info[k]);
+  return HX_OK;
+}
+
+hx_status build_chunk(Build& B, Instance& I, const WsLayout& W, int p0, int ch) {
+  double2* ops = reinterpret_cast<double2*>(B.plan->arena + I.d_ops) + (long long)p0 * I.pole_stride;
+  const int q2 = I.q2;
+  const double sx = 2.0 * I.mesh.nex / (I.mesh.x1 - I.mesh.x0);
+  const double sy = 2.0 * I.mesh.ney / (I.mesh.y1 - I.mesh.y0);
+  std::vector<double2> sig(ch);
+  for (int j = 0; j < ch; ++j) {
+    const cd s = std::pow(I.alpha[I.M + p0 + j] / I.tau, 2);
+    sig[j] = make_double2(s.real(), s.imag());
+  }
+  HX_TRY(upload(B, B.ws + W.sigma, sig.data(), sizeof(double2) * ch));
+
+  // leaf systems: assemble, factor, solve [W | S] in place, DtN maps
+  hx::LeafAssembleArgs la{};
+  la.c2 = wsp<double>(B, W.c2);
+  la.D = wsp<double>(B, W.D);
+  la.p = I.mesh.p;
+  la.q = I.q;
+  la.n_leaf = I.n_leaf;
+  la.chunk = ch;
+  la.sx = sx;
+  la.sy = sy;
+  la.sigma = wsp<double2>(B, W.sigma);
+  la.leaves = reinterpret_cast<const LeafDesc*>(B.plan->arena + I.d_leaves);
+  la.A = wsp<double2>(B, W.A);
+  la.ops = ops;
+  la.pole_stride = I.pole_stride;
+  HIP_OK(hx::launch_leaf_assemble(la, B.s));
+
+  // group leaves by edge count (same right-hand side width)
+  std::map<int, std::vector<int>> cls;
+  for (int l = 0; l < I.n_leaf; ++l) cls[I.leaves[l].e].push_back(l);
+  std::vector<void*> ptrs;
+  struct Call { int e, n; size_t pa, pb; long long piv; };
+  std::vector<Call> calls;
+  long long piv = 0;
+  for (auto& kv : cls) {
+    Call c{kv.first, (int)kv.second.size() * ch, ptrs.size(), 0, piv};
+    for (int j = 0; j < ch; ++j)
+      for (int l : kv.second) ptrs.push_back(wsp<double2>(B, W.A) + ((long long)j * I.n_leaf + l) * q2 * q2);
+    c.pb = ptrs.size();
+    for (int j = 0; j < ch; ++j)
+      for (int l : kv.second) ptrs.push_back(ops + (long long)j * I.pole_stride + I.leaves[l].op_off);
+    piv += (long long)c.n;
+    calls.push_back(c);
+  }
+  HX_TRY(upload(B, B.ws + W.ptr, ptrs.data(), sizeof(void*) * ptrs.size()));
+  void** dptr = wsp<void*>(B, W.ptr);
+  for (auto& c : calls) {
+    auto A = reinterpret_cast<rocblas_double_complex* const*>(dptr + c.pa);
+    auto R = reinterpret_cast<rocblas_double_complex* const*>(dptr + c.pb);
+    int* ipiv = wsp<int>(B, W.ipiv) + c.piv * q2;
+    int* info = wsp<int>(B, W.info) + c.piv;
+    RB_OK(rocsolver_zgetrf_batched(B.rb, q2, q2, A, q2, ipiv, q2, info, c.n));
+    RB_OK(rocsolver_zgetrs_batched(B.rb, rocblas_operation_none, q2, q2 + c.e, A, q2, ipiv, q2, R,
+                                   q2, c.n));
+  }
+  HX_TRY(check_info(B, W, piv, "element", 0));
+
+  // T offsets per leaf, then the DtN maps
+  std::vector<long long> toff(I.n_leaf);
+  long long t = 0;
+  for (int l = 0; l < I.n_leaf; ++l) { toff[l] = t; t += (long long)I.leaves[l].e * I.leaves[l].e; }
+  long long* d_toff = wsp<long long>(B, W.toff);
+  HX_TRY(upload(B, d_toff, toff.data(), sizeof(long long) * toff.size()));
+  hx::LeafDtnArgs ld{};
+  ld.D = la.D;
+  ld.p = I.mesh.p;
+  ld.q = I.q;
+  ld.n_leaf = I.n_leaf;
+  ld.chunk = ch;
+  ld.sx = sx;
+  ld.sy = sy;
+  ld.leaves = la.leaves;
+  ld.ops = ops;
+  ld.pole_stride = I.pole_stride;
+  ld.T = wsp<double2>(B, W.T0);
+  ld.T_stride = W.sizeT;
+  ld.T_off = d_toff;
+  HIP_OK(hx::launch_leaf_dtn(ld, B.s));
+
+  size_t Tc = W.T0, Tp = W.T1;
+  std::vector<long long> child_off = toff;
+  for (size_t lv = 1; lv < I.levels.size(); ++lv) {
+    const Level& L = I.levels[lv];
+    const int nb = (int)L.boxes.size();
+    std::vector<long long> moff(nb), voff(nb), poff(nb);
+    long long m = 0, v = 0, pt = 0;
+    for (int k = 0; k < nb; ++k) {
+      const BoxDesc& D = L.boxes[k];
+      const long long ext = D.n1 + D.n2;
+      moff[k] = m; m += (long long)D.n3 * D.n3;
+      voff[k] = v; v += ext * D.n3;
+      poff[k] = pt; pt += ext * ext;
+    }
+    // offsets: [child T | M | V | Tpar] in one upload
+    std::vector<long long> offs;
+    offs.insert(offs.end(), child_off.begin(), child_off.end());
+    offs.insert(offs.end(), moff.begin(), moff.end());
+    offs.insert(offs.end(), voff.begin(), voff.end());
+    offs.insert(offs.end(), poff.begin(), poff.end());
+    long long* d_offs = wsp<long long>(B, W.toff);
+    HX_TRY(upload(B, d_offs, offs.data(), sizeof(long long) * offs.size()));
+    double2* Mbuf = wsp<double2>(B, W.A);
+    double2* Vbuf = Mbuf + m * ch;
+    hx::MergeGatherArgs mg{};
+    mg.boxes = reinterpret_cast<const BoxDesc*>(B.plan->arena + L.d_boxes);
+    mg.idx = reinterpret_cast<const int*>(B.plan->arena + I.d_idx);
+    mg.chunk = ch;
+    mg.Tc = wsp<double2>(B, Tc);
+    mg.Tc_stride = W.sizeT;
+    mg.Tc_off = d_offs;
+    mg.M = Mbuf;
+    mg.M_stride = m;
+    mg.M_off = d_offs + child_off.size();
+    mg.V = Vbuf;
+    mg.V_stride = v;
+    mg.V_off = d_offs + child_off.size() + nb;
+    mg.Tp = wsp<double2>(B, Tp);
+    mg.Tp_stride = W.sizeT;
+    mg.Tp_off = d_offs + child_off.size() + 2 * nb;
+    mg.ops = ops;
+    mg.pole_stride = I.pole_stride;
+    HIP_OK(hx::launch_merge_gather(mg, nb, B.s));
+
+    // classes of identical shapes
+    std::map<std::tuple<int, int, int>, std::vector<int>> mc;
+    for (int k = 0; k < nb; ++k) mc[{L.boxes[k].n1, L.boxes[k].n2, L.boxes[k].n3}].push_back(k);
+    ptrs.clear();
+    struct MCall { int n1, n2, n3, n; size_t pM, pZ, pV, pX, pY, pT; long long piv; };
+    std::vector<MCall> mcalls;
+    long long mpiv = 0;
+    for (auto& kv : mc) {
+      MCall c{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+              (int)kv.second.size() * ch, 0, 0, 0, 0, 0, 0, mpiv};
+      const long long ext = c.n1 + c.n2;
+      auto push = [&](auto fn) {
+        const size_t at = ptrs.size();
+        for (int j = 0; j < ch; ++j)
+          for (int k : kv.second) ptrs.push_back(fn(j, k));
+        return at;
+      };
+      c.pM = push([&](int j, int k) -> void* { return Mbuf + (long long)j * m + moff[k]; });
+      c.pZ = push([&](int j, int k) -> void* { return ops + (long long)j * I.pole_stride + L.boxes[k].op_off; });
+      c.pV = push([&](int j, int k) -> void* { return Vbuf + (long long)j * v + voff[k]; });
+      c.pX = push([&](int j, int k) -> void* {
+        return ops + (long long)j * I.pole_stride + L.boxes[k].op_off + (long long)c.n3 * ext; });
+      c.pY = push([&](int j, int k) -> void* {
+        return ops + (long long)j * I.pole_stride + L.boxes[k].op_off + (long long)c.n3 * (ext + c.n3); });
+      c.pT = push([&](int j, int k) -> void* { return wsp<double2>(B, Tp) + (long long)j * W.sizeT + poff[k]; });
+      mpiv += c.n;
+      mcalls.push_back(c);
+    }
+    HX_TRY(upload(B, B.ws + W.ptr, ptrs.data(), sizeof(void*) * ptrs.size()));
+    const rocblas_double_complex one{1.0, 0.0}, zero{0.0, 0.0}, mone{-1.0, 0.0};
+    long long ipiv_off = 0;
+    for (auto& c : mcalls) {
+      using P = rocblas_double_complex* const*;
+      using CP = const rocblas_double_complex* const*;
+      const int ext = c.n1 + c.n2;
+      int* ipiv = wsp<int>(B, W.ipiv) + ipiv_off;
+      int* info = wsp<int>(B, W.info) + c.piv;
+      ipiv_off += (long long)c.n * c.n3;
+      RB_OK(rocsolver_zgetrf_batched(B.rb, c.n3, c.n3, (P)(dptr + c.pM), c.n3, ipiv, c.n3, info, c.n));
+      RB_OK(rocsolver_zgetrs_batched(B.rb, rocblas_operation_none, c.n3, ext + c.n3, (P)(dptr + c.pM),
+                                     c.n3, ipiv, c.n3, (P)(dptr + c.pZ), c.n3, c.n));
+      if (ext == 0) continue;
+      // Y = V X
+      RB_OK(rocblas_zgemm_batched(B.rb, rocblas_operation_none, rocblas_operation_none, ext, c.n3,
+                                  c.n3, &one, (CP)(dptr + c.pV), ext, (CP)(dptr + c.pX), c.n3, &zero,
+                                  (P)(dptr + c.pY), ext, c.n));
+      // T_par = diag(T11a, T22b) - V X B
+      if (lv + 1 < I.levels.size())
+        RB_OK(rocblas_zgemm_batched(B.rb, rocblas_operation_none, rocblas_operation_none, ext, ext,
+                                    c.n3, &mone, (CP)(dptr + c.pV), ext, (CP)(dptr + c.pZ), c.n3, &one,
+                                    (P)(dptr + c.pT), ext, c.n));
+    }
+    HX_TRY(check_info(B, W, mpiv, "merge", (int)lv));
+    std::swap(Tc, Tp);
+    child_off = poff;
+  }
+  return HX_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+
+extern "C" {
+
+const char* hx_status_str(int st) {
+  switch (st) {
+    case HX_OK: return "HX_OK";
+    case HX_EINVAL: return "HX_EINVAL";
+    case HX_ENOMEM: return "HX_ENOMEM";
+    case HX_ESINGULAR: return "HX_ESINGULAR";
+    case HX_EUNSTABLE: return "HX_EUNSTABLE";
+    case HX_EDEVICE: return "HX_EDEVICE";
+    case HX_ESTATE: return "HX_ESTATE";
+    case HX_ESTAGE: return "HX_ESTAGE";
+    default: return "HX_UNKNOWN";
+  }
+}
+
+const char* hx_last_error(void) { return g_last_error.c_str(); }
+
+hx_status hx_plan_create(hx_plan** out, int precision, int device, unsigned flags) {
+  g_last_error.clear();
+  if (!out) return fail(HX_EINVAL, "out is null");
+  *out = nullptr;
+  if (precision != HX_FP64) return fail(HX_EINVAL, "unsupported precision %d", precision);
+  if (device < 0) return fail(HX_EINVAL, "device %d", device);
+  if (flags & ~(HX_FLAG_ALLOW_UNSTABLE | HX_FLAG_NO_GRAPH | HX_FLAG_CHECK_STATE))
+    return fail(HX_EINVAL, "unknown flags 0x%x", flags);
+  hx_plan* p = new hx_plan;
+  p->device = device;
+  p->flags = flags;
+  *out = p;
+  return HX_OK;
+}
+
+hx_status hx_plan_add(hx_plan* plan, const hx_mesh* mesh, const hx_coeffs* coeffs, double tau,
+                      double delta, const hx_rational* rational, int nrhs, int* instance_id) {
+  g_last_error.clear();
+  if (!plan) return fail(HX_EINVAL, "plan is null");
+  if (plan->arena) return fail(HX_ESTAGE, "plan is already bound");
+  HX_TRY(validate_add(mesh, coeffs, tau, delta, rational, nrhs));
+  Instance I;
+  I.mesh = *mesh;
+  I.q = mesh->p - 2;
+  I.q2 = I.q * I.q;
+  I.n_leaf = mesh->nex * mesh->ney;
+  I.M = (rational->npoles - 1) / 2;
+  I.npole = I.M + 1;
+  I.nrhs = nrhs;
+  I.ncol = I.npole * nrhs;
+  I.tau = tau;
+  I.delta = delta;
+  I.c2.assign(coeffs->c2, coeffs->c2 + (size_t)I.n_leaf * mesh->p * mesh->p);
+  for (int k = 0; k < rational->npoles; ++k) {
+    I.alpha.emplace_back(rational->alpha[2 * k], rational->alpha[2 * k + 1]);
+    I.b.emplace_back(rational->b[2 * k], rational->b[2 * k + 1]);
+  }
+  check_fit(I);
+  if (I.max_abs_R > 1.0 + 1e-6 && !(plan->flags & HX_FLAG_ALLOW_UNSTABLE))
+    return fail(HX_EUNSTABLE, "max |R(ix)| = 1 + %.3g on the real line exceeds 1 + 1e-6",
+                I.max_abs_R - 1.0);
+  // pole table: folded poles m = 0..M
+  cd beta = 0.0;
+  for (auto& v : I.b) beta += v;
+  I.beta = beta.real();
+  for (int k = 0; k <= I.M; ++k) {
+    const cd a = I.alpha[I.M + k], bb = I.b[I.M + k];
+    const double f = (k == 0) ? 1.0 : 2.0;
+    const cd cu = f * bb, cv = f * bb * a;
+    PoleCoef pc;
+    pc.alpha = make_double2(a.real(), a.imag());
+    pc.cu = make_double2(cu.real(), cu.imag());
+    pc.cv = make_double2(cv.real(), cv.imag());
+    I.coef.push_back(pc);
+  }
+  const std::vector<double> D = cheb_diff(mesh->p);
+  for (int k = 1; k <= I.q; ++k) I.nrow.push_back(D[0 * mesh->p + k]);
+  for (int k = 1; k <= I.q; ++k) I.nrow.push_back(D[(mesh->p - 1) * mesh->p + k]);
+  build_tree(I);
+  for (auto& L : I.levels)
+    if (L.max_x > 4096 || L.max_n3 > 4096)
+      return fail(HX_EINVAL, "merge interface of %d nodes exceeds the 4096-node LDS limit", L.max_x);
+  plan->inst.push_back(std::move(I));
+  if (instance_id) *instance_id = (int)plan->inst.size() - 1;
+  layout_arena(plan);
+  return HX_OK;
+}
+
+hx_status hx_plan_query(const hx_plan* plan, hx_info* info) {
+  g_last_error.clear();
+  if (!plan || !info) return fail(HX_EINVAL, "null plan or info");
+  if (plan->inst.empty()) return fail(HX_ESTAGE, "plan has no instance");
+  hx_info r{};
+  r.arena_bytes = plan->arena_bytes;
+  r.max_abs_R = 0.0;
+  r.fit_X = 1e300;
+  size_t wmax = 0, wmin = 0;
+  for (auto& I : plan->inst) {
+    r.operator_bytes += sizeof(double2) * (size_t)(I.leaf_ops + I.merge_ops) * I.npole;
+    r.dof_state += 2LL * I.n_leaf * I.q2 * I.nrhs;
+    r.dof_nodes += 2LL * I.n_leaf * I.mesh.p * I.mesh.p * I.nrhs;
+    r.folded_poles += I.npole;
+    // every stored entry is read once per column per step
+    long long entries = 0;
+    for (auto& L : I.leaves) entries += (long long)I.q2 * (I.q2 + L.e);
+    for (size_t l = 1; l < I.levels.size(); ++l)
+      for (auto& B : I.levels[l].boxes) {
+        const long long ext = B.n1 + B.n2;
+        entries += (long long)B.n3 * (ext + B.n3) + ext * B.n3;
+      }
+    r.op_bytes_per_step += 16.0 * (double)entries * I.npole * I.nrhs;
+    r.flops_per_step += 8.0 * (double)entries * I.npole * I.nrhs;
+    r.max_abs_R = std::max(r.max_abs_R, I.max_abs_R);
+    r.fit_X = std::min(r.fit_X, I.fit_X);
+    r.sum_abs_b = std::max(r.sum_abs_b, I.sum_abs_b);
+    const size_t cap = (size_t)16 << 30;
+    size_t all = ws_layout(I, I.npole).total;
+    int ch = I.npole;
+    while (all > cap && ch > 1) all = ws_layout(I, --ch).total;
+    wmax = std::max(wmax, all);
+    wmin = std::max(wmin, ws_layout(I, 1).total);
+  }
+  r.n_instances = (int)plan->inst.size();
+  r.workspace_bytes = wmax;
+  r.workspace_min_bytes = wmin;
+  *info = r;
+  return HX_OK;
+}
+
+hx_status hx_plan_bind(hx_plan* plan, void* arena, size_t arena_bytes) {
+  g_last_error.clear();
+  if (!plan || !arena) return fail(HX_EINVAL, "null plan or arena");
+  if (plan->inst.empty()) return fail(HX_ESTAGE, "plan has no instance");
+  if (plan->arena) return fail(HX_ESTAGE, "plan is already bound");
+  if (reinterpret_cast<uintptr_t>(arena) % kAlign) return fail(HX_EINVAL, "arena not 256-byte aligned");
+  if (arena_bytes < plan->arena_bytes)
+    return fail(HX_ENOMEM, "arena of %zu bytes, %zu needed", arena_bytes, plan->arena_bytes);
+  HIP_OK(hipSetDevice(plan->device));
+  char* a = static_cast<char*>(arena);
+  for (auto& I : plan->inst) {
+    HIP_OK(hipMemcpy(a + I.d_leaves, I.leaves.data(), sizeof(LeafDesc) * I.leaves.size(), hipMemcpyHostToDevice));
+    if (!I.idx.empty())
+      HIP_OK(hipMemcpy(a + I.d_idx, I.idx.data(), sizeof(int) * I.idx.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(a + I.d_coef, I.coef.data(), sizeof(PoleCoef) * I.coef.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(a + I.d_nrow, I.nrow.data(), sizeof(double) * I.nrow.size(), hipMemcpyHostToDevice));
+    for (auto& L : I.levels)
+      if (!L.boxes.empty())
+        HIP_OK(hipMemcpy(a + L.d_boxes, L.boxes.data(), sizeof(BoxDesc) * L.boxes.size(), hipMemcpyHostToDevice));
+  }
+  plan->arena = a;
+  plan->d_flag = reinterpret_cast<int*>(a + plan->d_flag_off);
+  return HX_OK;
+}
+
+hx_status hx_plan_build(hx_plan* plan, void* workspace, size_t workspace_bytes, void* stream) {
+  g_last_error.clear();
+  if (!plan) return fail(HX_EINVAL, "plan is null");
+  if (!plan->arena) return fail(HX_ESTAGE, "plan is not bound");
+  if (!workspace) return fail(HX_EINVAL, "workspace is null");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(HX_EINVAL, "workspace not 256-byte aligned");
+  HIP_OK(hipSetDevice(plan->device));
+  Build B;
+  B.plan = plan;
+  B.s = static_cast<hipStream_t>(stream);
+  B.ws = static_cast<char*>(workspace);
+  B.ws_bytes = workspace_bytes;
+  RB_OK(rocblas_create_handle(&B.rb));
+  struct HandleGuard { rocblas_handle h; ~HandleGuard() { rocblas_destroy_handle(h); } } guard{B.rb};
+  RB_OK(rocblas_set_stream(B.rb, B.s));
+  plan->built = false;
+  for (auto& I : plan->inst) {
+    int ch = I.npole;
+    while (ch > 0 && ws_layout(I, ch).total > workspace_bytes) --ch;
+    if (ch == 0)
+      return fail(HX_ENOMEM, "workspace of %zu bytes, at least %zu needed", workspace_bytes,
+                  ws_layout(I, 1).total);
+    const WsLayout W = ws_layout(I, ch);
+    HX_TRY(upload(B, B.ws + W.c2, I.c2.data(), sizeof(double) * I.c2.size()));
+    const std::vector<double> D = cheb_diff(I.mesh.p);
+    HX_TRY(upload(B, B.ws + W.D, D.data(), sizeof(double) * D.size()));
+    for (int p0 = 0; p0 < I.npole; p0 += ch) HX_TRY(build_chunk(B, I, W, p0, std::min(ch, I.npole - p0)));
+  }
+  HIP_OK(hipStreamSynchronize(B.s));
+  plan->built = true;
+  return HX_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+hx_status enqueue_step(hx_plan* plan, double* const* states, hipStream_t s) {
+  char* a = plan->arena;
+  for (size_t k = 0; k < plan->inst.size(); ++k) {
+    Instance& I = plan->inst[k];
+    const double2* ops = reinterpret_cast<const double2*>(a + I.d_ops);
+    double2* w = reinterpret_cast<double2*>(a + I.d_w);
+    const auto* leaves = reinterpret_cast<const LeafDesc*>(a + I.d_leaves);
+    const auto* coef = reinterpret_cast<const PoleCoef*>(a + I.d_coef);
+    const int* idx = reinterpret_cast<const int*>(a + I.d_idx);
+    const long long n_int = (long long)I.n_leaf * I.q2;
+    auto lvl = [&](size_t l, size_t off) { return reinterpret_cast<double2*>(a + off); };
+
+    hx::LeafUpArgs lu{};
+    lu.ops = ops;
+    lu.pole_stride = I.pole_stride;
+    lu.leaves = leaves;
+    lu.ncol = I.ncol;
+    lu.nrhs = I.nrhs;
+    lu.state = states[k];
+    lu.rhs_stride = 2 * n_int;
+    lu.n_int = (int)n_int;
+    lu.coef = coef;
+    lu.inv_tau = 1.0 / I.tau;
+    lu.inv_tau2 = 1.0 / (I.tau * I.tau);
+    lu.nrow = reinterpret_cast<const double*>(a + I.d_nrow);
+    lu.sx = 2.0 * I.mesh.nex / (I.mesh.x1 - I.mesh.x0);
+    lu.sy = 2.0 * I.mesh.ney / (I.mesh.y1 - I.mesh.y0);
+    lu.q = I.q;
+    lu.w = w;
+    lu.w_col_stride = n_int;
+    lu.h = lvl(0, I.levels[0].d_h);
+    lu.h_col_stride = I.levels[0].total_ext;
+    HIP_OK(hx::launch_leaf_up(lu, I.n_leaf, s));
+
+    const size_t nl = I.levels.size();
+    for (size_t l = 1; l < nl; ++l) {
+      const Level& L = I.levels[l];
+      hx::MergeArgs m{};
+      m.ops = ops;
+      m.pole_stride = I.pole_stride;
+      m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
+      m.idx = idx;
+      m.ncol = I.ncol;
+      m.nrhs = I.nrhs;
+      m.row_blocks = std::max(1, (L.max_ext + hx::kBlock - 1) / hx::kBlock);
+      m.child = lvl(l - 1, I.levels[l - 1].d_h);
+      m.child_col_stride = I.levels[l - 1].total_ext;
+      m.self = lvl(l, L.d_h);
+      m.self_col_stride = L.total_ext;
+      m.g3 = lvl(l, L.d_g3);
+      m.g3_col_stride = L.total_n3;
+      HIP_OK(hx::launch_merge_up(m, (int)L.boxes.size(), L.max_n3, s));
+    }
+    for (size_t l = nl - 1; l >= 1; --l) {
+      const Level& L = I.levels[l];
+      hx::MergeArgs m{};
+      m.ops = ops;
+      m.pole_stride = I.pole_stride;
+      m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
+      m.idx = idx;
+      m.ncol = I.ncol;
+      m.nrhs = I.nrhs;
+      m.row_blocks = std::max(1, (L.max_n3 + hx::kBlock - 1) / hx::kBlock);
+      m.child = lvl(l - 1, I.levels[l - 1].d_u);
+      m.child_col_stride = I.levels[l - 1].total_ext;
+      m.self = lvl(l, L.d_u);
+      m.self_col_stride = L.total_ext;
+      m.g3 = lvl(l, L.d_g3);
+      m.g3_col_stride = L.total_n3;
+      HIP_OK(hx::launch_merge_down(m, (int)L.boxes.size(), L.max_x, s));
+    }
+    hx::LeafDownArgs ld{};
+    ld.ops = ops;
+    ld.pole_stride = I.pole_stride;
+    ld.leaves = leaves;
+    ld.ncol = I.ncol;
+    ld.nrhs = I.nrhs;
+    ld.q = I.q;
+    ld.u = lvl(0, I.levels[0].d_u);
+    ld.u_col_stride = I.levels[0].total_ext;
+    ld.w = w;
+    ld.w_col_stride = n_int;
+    HIP_OK(hx::launch_leaf_down(ld, I.n_leaf, s));
+
+    hx::PoleSumArgs ps{};
+    ps.leaves = leaves;
+    ps.npole = I.npole;
+    ps.nrhs = I.nrhs;
+    ps.q = I.q;
+    ps.coef = coef;
+    ps.y = w;
+    ps.y_col_stride = n_int;
+    ps.state = states[k];
+    ps.rhs_stride = 2 * n_int;
+    ps.n_int = (int)n_int;
+    ps.beta = I.beta;
+    ps.inv_tau = 1.0 / I.tau;
+    HIP_OK(hx::launch_pole_sum(ps, I.n_leaf, s));
+  }
+  return HX_OK;
+}
+
+void drop_graph(hx_plan* plan) {
+  if (plan->graph_exec) hipGraphExecDestroy(plan->graph_exec);
+  if (plan->graph) hipGraphDestroy(plan->graph);
+  plan->graph_exec = nullptr;
+  plan->graph = nullptr;
+  plan->graph_states.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+hx_status hx_step(hx_plan* plan, double* const* states, int n_steps, void* stream) {
+  g_last_error.clear();
+  if (!plan) return fail(HX_EINVAL, "plan is null");
+  if (!plan->built) return fail(HX_ESTAGE, "plan is not built");
+  if (!states) return fail(HX_EINVAL, "states is null");
+  if (n_steps < 0) return fail(HX_EINVAL, "n_steps = %d", n_steps);
+  for (size_t k = 0; k < plan->inst.size(); ++k)
+    if (!states[k]) return fail(HX_EINVAL, "state pointer %zu is null", k);
+  if (n_steps == 0) return HX_OK;
+  HIP_OK(hipSetDevice(plan->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (plan->flags & HX_FLAG_CHECK_STATE) {
+    HIP_OK(hipMemsetAsync(plan->d_flag, 0, sizeof(int), s));
+    for (size_t k = 0; k < plan->inst.size(); ++k) {
+      const Instance& I = plan->inst[k];
+      HIP_OK(hx::launch_nonfinite_check(states[k], 2LL * I.n_leaf * I.q2 * I.nrhs, plan->d_flag, s));
+    }
+    int flag = 0;
+    HIP_OK(hipMemcpyAsync(&flag, plan->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (flag) return fail(HX_ESTATE, "non-finite value in the state");
+  }
+  const bool use_graph = !(plan->flags & HX_FLAG_NO_GRAPH) && s != nullptr;
+  if (!use_graph) {
+    for (int n = 0; n < n_steps; ++n) HX_TRY(enqueue_step(plan, states, s));
+    return HX_OK;
+  }
+  std::vector<double*> key(states, states + plan->inst.size());
+  if (!plan->graph_exec || key != plan->graph_states) {
+    drop_graph(plan);
+    HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const hx_status st = enqueue_step(plan, states, s);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &g);
+    if (st != HX_OK) {
+      if (g) hipGraphDestroy(g);
+      return st;
+    }
+    HIP_OK(ec);
+    plan->graph = g;
+    HIP_OK(hipGraphInstantiate(&plan->graph_exec, g, nullptr, nullptr, 0));
+    plan->graph_states = key;
+  }
+  for (int n = 0; n < n_steps; ++n) HIP_OK(hipGraphLaunch(plan->graph_exec, s));
+  return HX_OK;
+}
+
+void hx_plan_destroy(hx_plan* plan) {
+  if (!plan) return;
+  drop_graph(plan);
+  delete plan;
+}
+
+}  // extern "C"
