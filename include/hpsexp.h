@@ -171,6 +171,22 @@ hx_status hx_plan_build(hx_plan* plan, void* workspace, size_t workspace_bytes,
  * n_steps < 0. */
 hx_status hx_step(hx_plan* plan, double* const* states, int n_steps, void* stream);
 
+/* Kernel classes reported by hx_step_profile. */
+#define HX_K_LEAF_UP    0  /* element upward pass: right-hand side, W g, N_i w   */
+#define HX_K_MERGE_UP   1  /* merge upward pass, one launch per tree level       */
+#define HX_K_MERGE_DOWN 2  /* merge downward pass, one launch per tree level     */
+#define HX_K_LEAF_DOWN  3  /* element downward pass: w - S u_e                   */
+#define HX_K_POLE_SUM   4  /* FP64 pole sum and velocity post-map                 */
+#define HX_K_CLASSES    5
+
+/* Diagnostic twin of hx_step: the same kernels, launched eagerly on
+ * `stream` with a HIP event pair around every launch.  kernel_ms[c] and
+ * launches[c] (arrays of n_classes entries, host) receive the summed
+ * duration in milliseconds and the launch count of kernel class c.
+ * Synchronous.  Errors as hx_step. */
+hx_status hx_step_profile(hx_plan* plan, double* const* states, int n_steps, void* stream,
+                          double* kernel_ms, int* launches, int n_classes);
+
 /* Name of a status code. */
 const char* hx_status_str(int status);
 

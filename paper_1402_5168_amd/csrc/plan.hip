@@ -821,7 +821,40 @@ hx_status hx_plan_build(hx_plan* plan, void* workspace, size_t workspace_bytes, 
 
 namespace {
 
-hx_status enqueue_step(hx_plan* plan, double* const* states, hipStream_t s) {
+// Event pairs around kernel launches (diagnostic profiling of a step).
+struct Prof {
+  std::vector<hipEvent_t> start, stop;
+  std::vector<int> cls;
+  hipStream_t s = nullptr;
+  hx_status begin(int c) {
+    hipEvent_t e;
+    HIP_OK(hipEventCreate(&e));
+    start.push_back(e);
+    cls.push_back(c);
+    HIP_OK(hipEventRecord(e, s));
+    return HX_OK;
+  }
+  hx_status end() {
+    hipEvent_t e;
+    HIP_OK(hipEventCreate(&e));
+    stop.push_back(e);
+    HIP_OK(hipEventRecord(e, s));
+    return HX_OK;
+  }
+  ~Prof() {
+    for (auto e : start) hipEventDestroy(e);
+    for (auto e : stop) hipEventDestroy(e);
+  }
+};
+
+#define TIMED(cls, launch)                      \
+  do {                                          \
+    if (prof) HX_TRY(prof->begin(cls));         \
+    HIP_OK(launch);                             \
+    if (prof) HX_TRY(prof->end());              \
+  } while (0)
+
+hx_status enqueue_step(hx_plan* plan, double* const* states, hipStream_t s, Prof* prof = nullptr) {
   char* a = plan->arena;
   for (size_t k = 0; k < plan->inst.size(); ++k) {
     Instance& I = plan->inst[k];
@@ -853,7 +886,7 @@ hx_status enqueue_step(hx_plan* plan, double* const* states, hipStream_t s) {
     lu.w_col_stride = n_int;
     lu.h = lvl(0, I.levels[0].d_h);
     lu.h_col_stride = I.levels[0].total_ext;
-    HIP_OK(hx::launch_leaf_up(lu, I.n_leaf, s));
+    TIMED(HX_K_LEAF_UP, hx::launch_leaf_up(lu, I.n_leaf, s));
 
     const size_t nl = I.levels.size();
     for (size_t l = 1; l < nl; ++l) {
@@ -872,7 +905,7 @@ hx_status enqueue_step(hx_plan* plan, double* const* states, hipStream_t s) {
       m.self_col_stride = L.total_ext;
       m.g3 = lvl(l, L.d_g3);
       m.g3_col_stride = L.total_n3;
-      HIP_OK(hx::launch_merge_up(m, (int)L.boxes.size(), L.max_n3, s));
+      TIMED(HX_K_MERGE_UP, hx::launch_merge_up(m, (int)L.boxes.size(), L.max_n3, s));
     }
     for (size_t l = nl - 1; l >= 1; --l) {
       const Level& L = I.levels[l];
@@ -890,7 +923,7 @@ hx_status enqueue_step(hx_plan* plan, double* const* states, hipStream_t s) {
       m.self_col_stride = L.total_ext;
       m.g3 = lvl(l, L.d_g3);
       m.g3_col_stride = L.total_n3;
-      HIP_OK(hx::launch_merge_down(m, (int)L.boxes.size(), L.max_x, s));
+      TIMED(HX_K_MERGE_DOWN, hx::launch_merge_down(m, (int)L.boxes.size(), L.max_x, s));
     }
     hx::LeafDownArgs ld{};
     ld.ops = ops;
@@ -903,7 +936,7 @@ hx_status enqueue_step(hx_plan* plan, double* const* states, hipStream_t s) {
     ld.u_col_stride = I.levels[0].total_ext;
     ld.w = w;
     ld.w_col_stride = n_int;
-    HIP_OK(hx::launch_leaf_down(ld, I.n_leaf, s));
+    TIMED(HX_K_LEAF_DOWN, hx::launch_leaf_down(ld, I.n_leaf, s));
 
     hx::PoleSumArgs ps{};
     ps.leaves = leaves;
@@ -918,7 +951,7 @@ hx_status enqueue_step(hx_plan* plan, double* const* states, hipStream_t s) {
     ps.n_int = (int)n_int;
     ps.beta = I.beta;
     ps.inv_tau = 1.0 / I.tau;
-    HIP_OK(hx::launch_pole_sum(ps, I.n_leaf, s));
+    TIMED(HX_K_POLE_SUM, hx::launch_pole_sum(ps, I.n_leaf, s));
   }
   return HX_OK;
 }
@@ -979,6 +1012,33 @@ hx_status hx_step(hx_plan* plan, double* const* states, int n_steps, void* strea
     plan->graph_states = key;
   }
   for (int n = 0; n < n_steps; ++n) HIP_OK(hipGraphLaunch(plan->graph_exec, s));
+  return HX_OK;
+}
+
+hx_status hx_step_profile(hx_plan* plan, double* const* states, int n_steps, void* stream,
+                          double* kernel_ms, int* launches, int n_classes) {
+  g_last_error.clear();
+  if (!plan) return fail(HX_EINVAL, "plan is null");
+  if (!plan->built) return fail(HX_ESTAGE, "plan is not built");
+  if (!states || !kernel_ms || !launches) return fail(HX_EINVAL, "null argument");
+  if (n_steps < 0 || n_classes < 0) return fail(HX_EINVAL, "negative count");
+  for (size_t k = 0; k < plan->inst.size(); ++k)
+    if (!states[k]) return fail(HX_EINVAL, "state pointer %zu is null", k);
+  for (int c = 0; c < n_classes; ++c) { kernel_ms[c] = 0.0; launches[c] = 0; }
+  HIP_OK(hipSetDevice(plan->device));
+  Prof prof;
+  prof.s = static_cast<hipStream_t>(stream);
+  for (int n = 0; n < n_steps; ++n) HX_TRY(enqueue_step(plan, states, prof.s, &prof));
+  HIP_OK(hipStreamSynchronize(prof.s));
+  for (size_t k = 0; k < prof.cls.size(); ++k) {
+    float ms = 0.0f;
+    HIP_OK(hipEventElapsedTime(&ms, prof.start[k], prof.stop[k]));
+    const int c = prof.cls[k];
+    if (c < n_classes) {
+      kernel_ms[c] += ms;
+      launches[c] += 1;
+    }
+  }
   return HX_OK;
 }
 

@@ -47,9 +47,13 @@ class hx_info(ctypes.Structure):
                 ("max_abs_R", c_double), ("fit_X", c_double), ("sum_abs_b", c_double)]
 
 
+HX_K_LEAF_UP, HX_K_MERGE_UP, HX_K_MERGE_DOWN, HX_K_LEAF_DOWN, HX_K_POLE_SUM = range(5)
+HX_K_CLASSES = 5
+KERNEL_NAMES = ("k_leaf_up", "k_merge_up", "k_merge_down", "k_leaf_down", "k_pole_sum")
+
 EXPORTS = ("hx_plan_create", "hx_plan_add", "hx_plan_query", "hx_plan_bind",
-           "hx_plan_build", "hx_step", "hx_status_str", "hx_last_error",
-           "hx_plan_destroy")
+           "hx_plan_build", "hx_step", "hx_step_profile", "hx_status_str",
+           "hx_last_error", "hx_plan_destroy")
 
 _lib = None
 
@@ -70,13 +74,15 @@ def load() -> ctypes.CDLL:
     lib.hx_plan_bind.argtypes = [c_void_p, c_void_p, c_size_t]
     lib.hx_plan_build.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p]
     lib.hx_step.argtypes = [c_void_p, POINTER(c_void_p), c_int, c_void_p]
+    lib.hx_step_profile.argtypes = [c_void_p, POINTER(c_void_p), c_int, c_void_p,
+                                    POINTER(c_double), POINTER(c_int), c_int]
     lib.hx_status_str.argtypes = [c_int]
     lib.hx_status_str.restype = c_char_p
     lib.hx_last_error.argtypes = []
     lib.hx_last_error.restype = c_char_p
     lib.hx_plan_destroy.argtypes = [c_void_p]
     lib.hx_plan_destroy.restype = None
-    for name in EXPORTS[:6]:
+    for name in EXPORTS[:7]:
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -127,6 +133,15 @@ def hx_plan_build(plan, ws_ptr: int, nbytes: int, stream: int = 0) -> None:
 def hx_step(plan, state_ptrs, n_steps: int, stream: int = 0) -> None:
     arr = (c_void_p * len(state_ptrs))(*[c_void_p(p) for p in state_ptrs])
     _check(load().hx_step(plan, arr, n_steps, c_void_p(stream)))
+
+
+def hx_step_profile(plan, state_ptrs, n_steps: int, stream: int = 0):
+    """Returns (milliseconds, launches) per kernel class."""
+    arr = (c_void_p * len(state_ptrs))(*[c_void_p(p) for p in state_ptrs])
+    ms = (c_double * HX_K_CLASSES)()
+    nl = (c_int * HX_K_CLASSES)()
+    _check(load().hx_step_profile(plan, arr, n_steps, c_void_p(stream), ms, nl, HX_K_CLASSES))
+    return list(ms), list(nl)
 
 
 def hx_status_str(status: int) -> str:
@@ -204,6 +219,12 @@ class Plan:
                 raise ValueError(f"state {k} has shape {tuple(x.shape)}, "
                                  f"expected {self.state_shape(k)}")
         hx_step(self.handle, [x.data_ptr() for x in states], n_steps, s.cuda_stream)
+
+    def step_profile(self, states, n_steps: int, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return hx_step_profile(self.handle, [x.data_ptr() for x in states], n_steps,
+                               s.cuda_stream)
 
     def close(self):
         if self.handle is not None:
