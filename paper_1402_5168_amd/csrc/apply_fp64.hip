@@ -32,23 +32,54 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
   return make_double2(a.x + b.x, a.y + b.y);
 }
 
-// acc += A[row + k*lda] * x[k], k = 0..n-1, with four loads in flight.
-__device__ __forceinline__ double2 col_dot(const double2* __restrict__ A, long long lda,
-                                           const double2* __restrict__ x, int n) {
+// Column-major matrix-vector product over the row block [r0, r0 + nr):
+//   out[t] = sum_{c < m} A[(r0 + t) + c*lda] x[c],  valid in thread t < nr.
+// The BS threads split into G = BS / nr column groups (G = 1 for tall
+// blocks), so short operators still keep every lane loading: group g reads
+// columns g, g+G, ...; at each step the block reads G*nr consecutive entries
+// when nr is the whole column.  Partials are summed through LDS in a fixed
+// order.  Must be called by every thread of the block.
+template <int BS>
+__device__ __forceinline__ double2 gemv_cm(const double2* __restrict__ A, long long lda, int r0,
+                                           int nr, int m, const double2* __restrict__ x,
+                                           double2* __restrict__ red) {
+  const int t = threadIdx.x;
+  const int G = nr >= BS ? 1 : BS / nr;
+  const int g = t / nr, r = t - g * nr;
   double2 a0 = make_double2(0.0, 0.0), a1 = a0;
-  int k = 0;
-  for (; k + 4 <= n; k += 4) {
-    const double2 m0 = ldnt(A + (k + 0) * lda);
-    const double2 m1 = ldnt(A + (k + 1) * lda);
-    const double2 m2 = ldnt(A + (k + 2) * lda);
-    const double2 m3 = ldnt(A + (k + 3) * lda);
-    cfma(a0, m0, x[k + 0]);
-    cfma(a1, m1, x[k + 1]);
-    cfma(a0, m2, x[k + 2]);
-    cfma(a1, m3, x[k + 3]);
+  if (g < G) {
+    const double2* Ar = A + r0 + r;
+    int c = g;
+    for (; c + 3 * G < m; c += 4 * G) {
+      const double2 m0 = ldnt(Ar + (long long)c * lda);
+      const double2 m1 = ldnt(Ar + (long long)(c + G) * lda);
+      const double2 m2 = ldnt(Ar + (long long)(c + 2 * G) * lda);
+      const double2 m3 = ldnt(Ar + (long long)(c + 3 * G) * lda);
+      cfma(a0, m0, x[c]);
+      cfma(a1, m1, x[c + G]);
+      cfma(a0, m2, x[c + 2 * G]);
+      cfma(a1, m3, x[c + 3 * G]);
+    }
+    for (; c < m; c += G) cfma(a0, ldnt(Ar + (long long)c * lda), x[c]);
   }
-  for (; k < n; ++k) cfma(a0, ldnt(A + k * lda), x[k]);
-  return cadd(a0, a1);
+  a0 = cadd(a0, a1);
+  if (G == 1) return a0;
+  red[t] = a0;
+  __syncthreads();
+  if (t < nr) {
+    for (int k = 1; k < G; ++k) a0 = cadd(a0, red[k * nr + t]);
+  }
+  __syncthreads();
+  return a0;
+}
+
+// Side s (0 left, 1 right, 2 bottom, 3 top) of the slot-th present side.
+__device__ __forceinline__ int side_of_slot(int mask, int slot) {
+  int seen = -1;
+  for (int k = 0; k < 4; ++k)
+    if ((mask >> k) & 1)
+      if (++seen == slot) return k;
+  return -1;
 }
 
 // Leaf upward pass (one block per leaf and column):
@@ -57,6 +88,7 @@ __device__ __forceinline__ double2 col_dot(const double2* __restrict__ A, long l
 __global__ __launch_bounds__(kBlock) void k_leaf_up(LeafUpArgs a) {
   __shared__ double2 gs[kMaxQ2];
   __shared__ double2 ws[kMaxQ2];
+  __shared__ double2 red[kBlock];
   const int leaf = blockIdx.x / a.ncol;
   const int col = blockIdx.x - leaf * a.ncol;
   const int pole = col / a.nrhs, rhs = col - pole * a.nrhs;
@@ -71,20 +103,16 @@ __global__ __launch_bounds__(kBlock) void k_leaf_up(LeafUpArgs a) {
   }
   __syncthreads();
   const double2* W = a.ops + pole * a.pole_stride + L.op_off;
-  double2* wout = a.w + col * a.w_col_stride + (long long)leaf * q2;
-  for (int t = threadIdx.x; t < q2; t += blockDim.x) {
-    const double2 acc = col_dot(W + t, q2, gs, q2);
-    wout[t] = acc;
-    ws[t] = acc;
+  const double2 acc = gemv_cm<kBlock>(W, q2, 0, q2, q2, gs, red);
+  if (threadIdx.x < q2) {
+    a.w[col * a.w_col_stride + (long long)leaf * q2 + threadIdx.x] = acc;
+    ws[threadIdx.x] = acc;
   }
   __syncthreads();
   double2* hout = a.h + col * a.h_col_stride + L.vec_off;
   for (int r = threadIdx.x; r < L.e; r += blockDim.x) {
     const int slot = r / q, t = r - slot * q;
-    int s = -1, seen = -1;
-    for (int k = 0; k < 4; ++k)
-      if ((L.side_mask >> k) & 1)
-        if (++seen == slot) { s = k; break; }
+    const int s = side_of_slot(L.side_mask, slot);
     const double* nr = a.nrow + ((s == 1 || s == 3) ? q : 0);
     const double sc = (s == 0) ? -a.sx : (s == 1) ? a.sx : (s == 2) ? -a.sy : a.sy;
     double2 sum = make_double2(0.0, 0.0);
@@ -101,6 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_up(LeafUpArgs a) {
 //   g3 = h_3^a + h_3^b,   h_par = [h_1^a; h_2^b] - Y g3.
 __global__ __launch_bounds__(kBlock) void k_merge_up(MergeArgs a) {
   extern __shared__ double2 xs[];
+  __shared__ double2 red[kBlock];
   const int per_box = a.ncol * a.row_blocks;
   const int box = blockIdx.x / per_box;
   const int rem = blockIdx.x - box * per_box;
@@ -108,6 +137,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_up(MergeArgs a) {
   const int pole = col / a.nrhs;
   const BoxDesc B = a.boxes[box];
   const int n1 = B.n1, n2 = B.n2, n3 = B.n3, ext = n1 + n2;
+  const int r0 = rb * kBlock;
+  if (r0 >= ext && !(rb == 0 && ext == 0)) return;
   const int* i1 = a.idx + B.idx_off;
   const int* i2 = i1 + n1;
   const int* i3a = i2 + n2;
@@ -120,18 +151,22 @@ __global__ __launch_bounds__(kBlock) void k_merge_up(MergeArgs a) {
     double2* g3 = a.g3 + col * a.g3_col_stride + B.g3_off;
     for (int t = threadIdx.x; t < n3; t += blockDim.x) g3[t] = xs[t];
   }
-  const int r = rb * blockDim.x + threadIdx.x;
-  if (r >= ext) return;
+  if (ext == 0) return;
+  const int nr = min(ext - r0, kBlock);
   const double2* Y = a.ops + pole * a.pole_stride + B.op_off + (long long)n3 * (ext + n3);
-  const double2 acc = col_dot(Y + r, ext, xs, n3);
-  const double2 base = (r < n1) ? hc[B.a_vec + i1[r]] : hc[B.b_vec + i2[r - n1]];
-  a.self[col * a.self_col_stride + B.vec_off + r] = make_double2(base.x - acc.x, base.y - acc.y);
+  const double2 acc = gemv_cm<kBlock>(Y, ext, r0, nr, n3, xs, red);
+  const int r = r0 + threadIdx.x;
+  if (threadIdx.x < nr) {
+    const double2 base = (r < n1) ? hc[B.a_vec + i1[r]] : hc[B.b_vec + i2[r - n1]];
+    a.self[col * a.self_col_stride + B.vec_off + r] = make_double2(base.x - acc.x, base.y - acc.y);
+  }
 }
 
 // Merge downward pass for one level (block = box, column, row block):
 //   u3 = -Z [u_ext; g3], scattered with u_ext into the children's vectors.
 __global__ __launch_bounds__(kBlock) void k_merge_down(MergeArgs a) {
   extern __shared__ double2 xs[];
+  __shared__ double2 red[kBlock];
   const int per_box = a.ncol * a.row_blocks;
   const int box = blockIdx.x / per_box;
   const int rem = blockIdx.x - box * per_box;
@@ -139,6 +174,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_down(MergeArgs a) {
   const int pole = col / a.nrhs;
   const BoxDesc B = a.boxes[box];
   const int n1 = B.n1, n2 = B.n2, n3 = B.n3, ext = n1 + n2;
+  const int r0 = rb * kBlock;
+  if (r0 >= n3) return;
   const int* i1 = a.idx + B.idx_off;
   const int* i2 = i1 + n1;
   const int* i3a = i2 + n2;
@@ -153,18 +190,21 @@ __global__ __launch_bounds__(kBlock) void k_merge_down(MergeArgs a) {
     for (int k = threadIdx.x; k < n1; k += blockDim.x) uc[B.a_vec + i1[k]] = xs[k];
     for (int k = threadIdx.x; k < n2; k += blockDim.x) uc[B.b_vec + i2[k]] = xs[n1 + k];
   }
-  const int r = rb * blockDim.x + threadIdx.x;
-  if (r >= n3) return;
+  const int nr = min(n3 - r0, kBlock);
   const double2* Z = a.ops + pole * a.pole_stride + B.op_off;
-  const double2 acc = col_dot(Z + r, n3, xs, ext + n3);
-  const double2 u3 = make_double2(-acc.x, -acc.y);
-  uc[B.a_vec + i3a[r]] = u3;
-  uc[B.b_vec + i3b[r]] = u3;
+  const double2 acc = gemv_cm<kBlock>(Z, n3, r0, nr, ext + n3, xs, red);
+  if (threadIdx.x < nr) {
+    const int r = r0 + threadIdx.x;
+    const double2 u3 = make_double2(-acc.x, -acc.y);
+    uc[B.a_vec + i3a[r]] = u3;
+    uc[B.b_vec + i3b[r]] = u3;
+  }
 }
 
 // Leaf downward pass (block = leaf, column): y = w - S u_e, in place of w.
 __global__ __launch_bounds__(kBlock) void k_leaf_down(LeafDownArgs a) {
   __shared__ double2 us[4 * (kMaxP - 2)];
+  __shared__ double2 red[kBlock];
   const int leaf = blockIdx.x / a.ncol;
   const int col = blockIdx.x - leaf * a.ncol;
   const int pole = col / a.nrhs;
@@ -174,11 +214,11 @@ __global__ __launch_bounds__(kBlock) void k_leaf_down(LeafDownArgs a) {
   for (int c = threadIdx.x; c < L.e; c += blockDim.x) us[c] = ue[c];
   __syncthreads();
   const double2* S = a.ops + pole * a.pole_stride + L.op_off + (long long)q2 * q2;
-  double2* w = a.w + col * a.w_col_stride + (long long)leaf * q2;
-  for (int t = threadIdx.x; t < q2; t += blockDim.x) {
-    const double2 acc = col_dot(S + t, q2, us, L.e);
-    const double2 wt = w[t];
-    w[t] = make_double2(wt.x - acc.x, wt.y - acc.y);
+  const double2 acc = gemv_cm<kBlock>(S, q2, 0, q2, L.e, us, red);
+  if (threadIdx.x < q2) {
+    double2* w = a.w + col * a.w_col_stride + (long long)leaf * q2;
+    const double2 wt = w[threadIdx.x];
+    w[threadIdx.x] = make_double2(wt.x - acc.x, wt.y - acc.y);
   }
 }
 
