@@ -73,6 +73,9 @@ typedef enum {
 #define HX_FLAG_ALLOW_UNSTABLE 0x1u /* accept max|R(ix)| > 1 + 1e-6        */
 #define HX_FLAG_NO_GRAPH       0x2u /* launch kernels eagerly, no hipGraph  */
 #define HX_FLAG_CHECK_STATE    0x4u /* hx_step rejects non-finite states    */
+#define HX_FLAG_UNBATCHED      0x8u /* one pass per right-hand side instead of
+                                       batching them on the matrix cores
+                                       (reference for the batching speedup)  */
 
 /* Mesh: [x0,x1] x [y0,y1] split into nex x ney equal elements, each with a
  * p x p Chebyshev-Lobatto grid (section 2.2).  nex and ney are powers of

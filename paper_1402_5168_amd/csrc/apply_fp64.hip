@@ -105,11 +105,11 @@ __global__ __launch_bounds__(kBlock) void k_leaf_up(LeafUpArgs a) {
   const double2* W = a.ops + pole * a.pole_stride + L.op_off;
   const double2 acc = gemv_cm<kBlock>(W, q2, 0, q2, q2, gs, red);
   if (threadIdx.x < q2) {
-    a.w[col * a.w_col_stride + (long long)leaf * q2 + threadIdx.x] = acc;
+    a.w[((long long)pole * a.w_pole + (long long)leaf * q2 + threadIdx.x) * a.nrhs + rhs] = acc;
     ws[threadIdx.x] = acc;
   }
   __syncthreads();
-  double2* hout = a.h + col * a.h_col_stride + L.vec_off;
+  double2* hout = a.h + ((long long)pole * a.h_pole + L.vec_off) * a.nrhs + rhs;
   for (int r = threadIdx.x; r < L.e; r += blockDim.x) {
     const int slot = r / q, t = r - slot * q;
     const int s = side_of_slot(L.side_mask, slot);
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_up(LeafUpArgs a) {
     } else {
       for (int k = 0; k < q; ++k) { sum.x += nr[k] * ws[t + q * k].x; sum.y += nr[k] * ws[t + q * k].y; }
     }
-    hout[r] = make_double2(sc * sum.x, sc * sum.y);
+    hout[(long long)r * a.nrhs] = make_double2(sc * sum.x, sc * sum.y);
   }
 }
 
@@ -134,7 +134,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_up(MergeArgs a) {
   const int box = blockIdx.x / per_box;
   const int rem = blockIdx.x - box * per_box;
   const int col = rem / a.row_blocks, rb = rem - col * a.row_blocks;
-  const int pole = col / a.nrhs;
+  const int pole = col / a.nrhs, rhs = col - pole * a.nrhs;
+  const int R = a.nrhs;
   const BoxDesc B = a.boxes[box];
   const int n1 = B.n1, n2 = B.n2, n3 = B.n3, ext = n1 + n2;
   const int r0 = rb * kBlock;
@@ -143,13 +144,13 @@ __global__ __launch_bounds__(kBlock) void k_merge_up(MergeArgs a) {
   const int* i2 = i1 + n1;
   const int* i3a = i2 + n2;
   const int* i3b = i3a + n3;
-  const double2* hc = a.child + col * a.child_col_stride;
+  const double2* hc = a.child + (long long)pole * a.child_pole * R + rhs;
   for (int t = threadIdx.x; t < n3; t += blockDim.x)
-    xs[t] = cadd(hc[B.a_vec + i3a[t]], hc[B.b_vec + i3b[t]]);
+    xs[t] = cadd(hc[(long long)(B.a_vec + i3a[t]) * R], hc[(long long)(B.b_vec + i3b[t]) * R]);
   __syncthreads();
   if (rb == 0) {
-    double2* g3 = a.g3 + col * a.g3_col_stride + B.g3_off;
-    for (int t = threadIdx.x; t < n3; t += blockDim.x) g3[t] = xs[t];
+    double2* g3 = a.g3 + ((long long)pole * a.g3_pole + B.g3_off) * R + rhs;
+    for (int t = threadIdx.x; t < n3; t += blockDim.x) g3[(long long)t * R] = xs[t];
   }
   if (ext == 0) return;
   const int nr = min(ext - r0, kBlock);
@@ -157,8 +158,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_up(MergeArgs a) {
   const double2 acc = gemv_cm<kBlock>(Y, ext, r0, nr, n3, xs, red);
   const int r = r0 + threadIdx.x;
   if (threadIdx.x < nr) {
-    const double2 base = (r < n1) ? hc[B.a_vec + i1[r]] : hc[B.b_vec + i2[r - n1]];
-    a.self[col * a.self_col_stride + B.vec_off + r] = make_double2(base.x - acc.x, base.y - acc.y);
+    const double2 base = (r < n1) ? hc[(long long)(B.a_vec + i1[r]) * R] : hc[(long long)(B.b_vec + i2[r - n1]) * R];
+    a.self[((long long)pole * a.self_pole + B.vec_off + r) * R + rhs] = make_double2(base.x - acc.x, base.y - acc.y);
   }
 }
 
@@ -171,7 +172,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_down(MergeArgs a) {
   const int box = blockIdx.x / per_box;
   const int rem = blockIdx.x - box * per_box;
   const int col = rem / a.row_blocks, rb = rem - col * a.row_blocks;
-  const int pole = col / a.nrhs;
+  const int pole = col / a.nrhs, rhs = col - pole * a.nrhs;
+  const int R = a.nrhs;
   const BoxDesc B = a.boxes[box];
   const int n1 = B.n1, n2 = B.n2, n3 = B.n3, ext = n1 + n2;
   const int r0 = rb * kBlock;
@@ -180,15 +182,15 @@ __global__ __launch_bounds__(kBlock) void k_merge_down(MergeArgs a) {
   const int* i2 = i1 + n1;
   const int* i3a = i2 + n2;
   const int* i3b = i3a + n3;
-  const double2* up = a.self + col * a.self_col_stride + B.vec_off;
-  const double2* g3 = a.g3 + col * a.g3_col_stride + B.g3_off;
-  for (int t = threadIdx.x; t < ext; t += blockDim.x) xs[t] = up[t];
-  for (int t = threadIdx.x; t < n3; t += blockDim.x) xs[ext + t] = g3[t];
+  const double2* up = a.self + ((long long)pole * a.self_pole + B.vec_off) * R + rhs;
+  const double2* g3 = a.g3 + ((long long)pole * a.g3_pole + B.g3_off) * R + rhs;
+  for (int t = threadIdx.x; t < ext; t += blockDim.x) xs[t] = up[(long long)t * R];
+  for (int t = threadIdx.x; t < n3; t += blockDim.x) xs[ext + t] = g3[(long long)t * R];
   __syncthreads();
-  double2* uc = a.child + col * a.child_col_stride;
+  double2* uc = a.child + (long long)pole * a.child_pole * R + rhs;
   if (rb == 0) {
-    for (int k = threadIdx.x; k < n1; k += blockDim.x) uc[B.a_vec + i1[k]] = xs[k];
-    for (int k = threadIdx.x; k < n2; k += blockDim.x) uc[B.b_vec + i2[k]] = xs[n1 + k];
+    for (int k = threadIdx.x; k < n1; k += blockDim.x) uc[(long long)(B.a_vec + i1[k]) * R] = xs[k];
+    for (int k = threadIdx.x; k < n2; k += blockDim.x) uc[(long long)(B.b_vec + i2[k]) * R] = xs[n1 + k];
   }
   const int nr = min(n3 - r0, kBlock);
   const double2* Z = a.ops + pole * a.pole_stride + B.op_off;
@@ -196,8 +198,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_down(MergeArgs a) {
   if (threadIdx.x < nr) {
     const int r = r0 + threadIdx.x;
     const double2 u3 = make_double2(-acc.x, -acc.y);
-    uc[B.a_vec + i3a[r]] = u3;
-    uc[B.b_vec + i3b[r]] = u3;
+    uc[(long long)(B.a_vec + i3a[r]) * R] = u3;
+    uc[(long long)(B.b_vec + i3b[r]) * R] = u3;
   }
 }
 
@@ -207,18 +209,19 @@ __global__ __launch_bounds__(kBlock) void k_leaf_down(LeafDownArgs a) {
   __shared__ double2 red[kBlock];
   const int leaf = blockIdx.x / a.ncol;
   const int col = blockIdx.x - leaf * a.ncol;
-  const int pole = col / a.nrhs;
+  const int pole = col / a.nrhs, rhs = col - pole * a.nrhs;
+  const int R = a.nrhs;
   const int q2 = a.q * a.q;
   const LeafDesc L = a.leaves[leaf];
-  const double2* ue = a.u + col * a.u_col_stride + L.vec_off;
-  for (int c = threadIdx.x; c < L.e; c += blockDim.x) us[c] = ue[c];
+  const double2* ue = a.u + ((long long)pole * a.u_pole + L.vec_off) * R + rhs;
+  for (int c = threadIdx.x; c < L.e; c += blockDim.x) us[c] = ue[(long long)c * R];
   __syncthreads();
   const double2* S = a.ops + pole * a.pole_stride + L.op_off + (long long)q2 * q2;
   const double2 acc = gemv_cm<kBlock>(S, q2, 0, q2, L.e, us, red);
   if (threadIdx.x < q2) {
-    double2* w = a.w + col * a.w_col_stride + (long long)leaf * q2;
-    const double2 wt = w[threadIdx.x];
-    w[threadIdx.x] = make_double2(wt.x - acc.x, wt.y - acc.y);
+    double2* w = a.w + ((long long)pole * a.w_pole + (long long)leaf * q2 + threadIdx.x) * R + rhs;
+    const double2 wt = *w;
+    *w = make_double2(wt.x - acc.x, wt.y - acc.y);
   }
 }
 
@@ -234,8 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_pole_sum(PoleSumArgs a) {
   for (int t = threadIdx.x; t < q2; t += blockDim.x) {
     double su = 0.0, sv = 0.0;
     for (int pole = 0; pole < a.npole; ++pole) {
-      const int col = pole * a.nrhs + rhs;
-      const double2 y = a.y[col * a.y_col_stride + (long long)leaf * q2 + t];
+      const double2 y = a.y[((long long)pole * a.y_pole + (long long)leaf * q2 + t) * a.nrhs + rhs];
       const PoleCoef c = a.coef[pole];
       su = fma(c.cu.x, y.x, fma(-c.cu.y, y.y, su));
       sv = fma(c.cv.x, y.x, fma(-c.cv.y, y.y, sv));

@@ -22,10 +22,10 @@ struct LeafUpArgs {
   const double* nrow;        // D[0][1..q] then D[p-1][1..q]
   double sx, sy;             // 2/hx, 2/hy
   int q;
-  double2* w;                // [col][leaf][q*q]
-  long long w_col_stride;
-  double2* h;                // level-0 h: [col][sum of e]
-  long long h_col_stride;
+  double2* w;                // [pole][leaf][q*q][rhs]
+  long long w_pole;          // nodes per pole: n_leaf * q*q
+  double2* h;                // level-0 h: [pole][sum of e][rhs]
+  long long h_pole;
 };
 
 struct MergeArgs {
@@ -34,12 +34,12 @@ struct MergeArgs {
   const BoxDesc* boxes;
   const int* idx;
   int ncol, nrhs, row_blocks;
-  double2* child;            // level below: h (up) or u (down), [col][...]
-  long long child_col_stride;
+  double2* child;            // level below: h (up) or u (down), [pole][node][rhs]
+  long long child_pole;      // nodes per pole in that level
   double2* self;             // this level: h (up, written) or u (down, read)
-  long long self_col_stride;
-  double2* g3;               // this level's interface loads [col][...]
-  long long g3_col_stride;
+  long long self_pole;
+  double2* g3;               // this level's interface loads [pole][node][rhs]
+  long long g3_pole;
 };
 
 struct LeafDownArgs {
@@ -47,18 +47,18 @@ struct LeafDownArgs {
   long long pole_stride;
   const LeafDesc* leaves;
   int ncol, nrhs, q;
-  const double2* u;          // level-0 u: [col][sum of e]
-  long long u_col_stride;
-  double2* w;                // in: w, out: y
-  long long w_col_stride;
+  const double2* u;          // level-0 u: [pole][sum of e][rhs]
+  long long u_pole;
+  double2* w;                // in: w, out: y   [pole][leaf][q*q][rhs]
+  long long w_pole;
 };
 
 struct PoleSumArgs {
   const LeafDesc* leaves;
   int npole, nrhs, q;
   const PoleCoef* coef;
-  const double2* y;
-  long long y_col_stride;
+  const double2* y;          // [pole][leaf][q*q][rhs]
+  long long y_pole;
   double* state;
   long long rhs_stride;
   int n_int;
@@ -70,6 +70,71 @@ hipError_t launch_merge_up(const MergeArgs& a, int n_box, int max_n3, hipStream_
 hipError_t launch_merge_down(const MergeArgs& a, int n_box, int max_x, hipStream_t s);
 hipError_t launch_leaf_down(const LeafDownArgs& a, int n_leaf, hipStream_t s);
 hipError_t launch_pole_sum(const PoleSumArgs& a, int n_leaf, hipStream_t s);
+
+// ---- solve stage, many right-hand sides (matrix cores) -----------------------
+
+template <class T> struct Cplx;
+template <> struct Cplx<double> { typedef double2 type; };
+template <> struct Cplx<float> { typedef float2 type; };
+
+template <class T>
+struct MmLeafUpArgs {
+  const typename Cplx<T>::type* ops;
+  long long pole_stride;
+  const LeafDesc* leaves;
+  int npole, nrhs, q;
+  const double* state;
+  long long rhs_stride;
+  int n_int;
+  const PoleCoef* coef;
+  double inv_tau, inv_tau2;
+  const double* nrow;
+  double sx, sy;
+  typename Cplx<T>::type* w;   // [pole][leaf][q*q][rhs]
+  long long w_pole;
+  typename Cplx<T>::type* h;   // [pole][sum of e][rhs]
+  long long h_pole;
+};
+
+template <class T>
+struct MmMergeArgs {
+  const typename Cplx<T>::type* ops;
+  long long pole_stride;
+  const BoxDesc* boxes;
+  const int* idx;
+  int npole, nrhs, row_groups;
+  typename Cplx<T>::type* child;
+  long long child_pole;
+  typename Cplx<T>::type* self;
+  long long self_pole;
+  typename Cplx<T>::type* g3;
+  long long g3_pole;
+};
+
+template <class T>
+struct MmLeafDownArgs {
+  const typename Cplx<T>::type* ops;
+  long long pole_stride;
+  const LeafDesc* leaves;
+  int npole, nrhs, q, row_groups;
+  const typename Cplx<T>::type* u;
+  long long u_pole;
+  typename Cplx<T>::type* w;
+  long long w_pole;
+  // pole sum (fused variant only)
+  const PoleCoef* coef;
+  double* state;
+  long long rhs_stride;
+  int n_int;
+  double beta, inv_tau;
+};
+
+// nt = right-hand-side tiles of 16 per block (1 or 2)
+template <class T> hipError_t launch_leaf_up_mm(const MmLeafUpArgs<T>& a, int n_leaf, int nt, hipStream_t s);
+template <class T> hipError_t launch_merge_up_mm(const MmMergeArgs<T>& a, int n_box, int nt, hipStream_t s);
+template <class T> hipError_t launch_merge_down_mm(const MmMergeArgs<T>& a, int n_box, int nt, hipStream_t s);
+template <class T> hipError_t launch_leaf_down_mm(const MmLeafDownArgs<T>& a, int n_leaf, int nt, hipStream_t s);
+template <class T> hipError_t launch_leaf_down_sum_mm(const MmLeafDownArgs<T>& a, int n_leaf, int nt, hipStream_t s);
 
 // ---- build stage ------------------------------------------------------------
 

@@ -656,7 +656,7 @@ hx_status hx_plan_create(hx_plan** out, int precision, int device, unsigned flag
   *out = nullptr;
   if (precision != HX_FP64) return fail(HX_EINVAL, "unsupported precision %d", precision);
   if (device < 0) return fail(HX_EINVAL, "device %d", device);
-  if (flags & ~(HX_FLAG_ALLOW_UNSTABLE | HX_FLAG_NO_GRAPH | HX_FLAG_CHECK_STATE))
+  if (flags & ~(HX_FLAG_ALLOW_UNSTABLE | HX_FLAG_NO_GRAPH | HX_FLAG_CHECK_STATE | HX_FLAG_UNBATCHED))
     return fail(HX_EINVAL, "unknown flags 0x%x", flags);
   hx_plan* p = new hx_plan;
   p->device = device;
@@ -854,98 +854,206 @@ struct Prof {
     if (prof) HX_TRY(prof->end());              \
   } while (0)
 
+// Many right-hand sides go through the matrix-core kernels unless the plan
+// asks for one launch per right-hand side (the unbatched reference).
+bool batched(const hx_plan* plan, const Instance& I) {
+  return I.nrhs > 1 && !(plan->flags & HX_FLAG_UNBATCHED);
+}
+
+hx_status enqueue_batched(hx_plan* plan, const Instance& I, double* state, hipStream_t s, Prof* prof) {
+  char* a = plan->arena;
+  const double2* ops = reinterpret_cast<const double2*>(a + I.d_ops);
+  double2* w = reinterpret_cast<double2*>(a + I.d_w);
+  const auto* leaves = reinterpret_cast<const LeafDesc*>(a + I.d_leaves);
+  const auto* coef = reinterpret_cast<const PoleCoef*>(a + I.d_coef);
+  const int* idx = reinterpret_cast<const int*>(a + I.d_idx);
+  const long long n_int = (long long)I.n_leaf * I.q2;
+  auto vec = [&](size_t off) { return reinterpret_cast<double2*>(a + off); };
+  const int nt = I.nrhs > 16 ? 2 : 1;
+
+  hx::MmLeafUpArgs<double> lu{};
+  lu.ops = ops;
+  lu.pole_stride = I.pole_stride;
+  lu.leaves = leaves;
+  lu.npole = I.npole;
+  lu.nrhs = I.nrhs;
+  lu.q = I.q;
+  lu.state = state;
+  lu.rhs_stride = 2 * n_int;
+  lu.n_int = (int)n_int;
+  lu.coef = coef;
+  lu.inv_tau = 1.0 / I.tau;
+  lu.inv_tau2 = 1.0 / (I.tau * I.tau);
+  lu.nrow = reinterpret_cast<const double*>(a + I.d_nrow);
+  lu.sx = 2.0 * I.mesh.nex / (I.mesh.x1 - I.mesh.x0);
+  lu.sy = 2.0 * I.mesh.ney / (I.mesh.y1 - I.mesh.y0);
+  lu.w = w;
+  lu.w_pole = n_int;
+  lu.h = vec(I.levels[0].d_h);
+  lu.h_pole = I.levels[0].total_ext;
+  TIMED(HX_K_LEAF_UP, hx::launch_leaf_up_mm<double>(lu, I.n_leaf, nt, s));
+
+  const size_t nl = I.levels.size();
+  for (size_t l = 1; l < nl; ++l) {
+    const Level& L = I.levels[l];
+    hx::MmMergeArgs<double> m{};
+    m.ops = ops;
+    m.pole_stride = I.pole_stride;
+    m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
+    m.idx = idx;
+    m.npole = I.npole;
+    m.nrhs = I.nrhs;
+    m.row_groups = std::max(1, (L.max_ext + 63) / 64);
+    m.child = vec(I.levels[l - 1].d_h);
+    m.child_pole = I.levels[l - 1].total_ext;
+    m.self = vec(L.d_h);
+    m.self_pole = L.total_ext;
+    m.g3 = vec(L.d_g3);
+    m.g3_pole = L.total_n3;
+    TIMED(HX_K_MERGE_UP, hx::launch_merge_up_mm<double>(m, (int)L.boxes.size(), nt, s));
+  }
+  for (size_t l = nl - 1; l >= 1; --l) {
+    const Level& L = I.levels[l];
+    hx::MmMergeArgs<double> m{};
+    m.ops = ops;
+    m.pole_stride = I.pole_stride;
+    m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
+    m.idx = idx;
+    m.npole = I.npole;
+    m.nrhs = I.nrhs;
+    m.row_groups = std::max(1, (L.max_n3 + 63) / 64);
+    m.child = vec(I.levels[l - 1].d_u);
+    m.child_pole = I.levels[l - 1].total_ext;
+    m.self = vec(L.d_u);
+    m.self_pole = L.total_ext;
+    m.g3 = vec(L.d_g3);
+    m.g3_pole = L.total_n3;
+    TIMED(HX_K_MERGE_DOWN, hx::launch_merge_down_mm<double>(m, (int)L.boxes.size(), nt, s));
+  }
+  hx::MmLeafDownArgs<double> ld{};
+  ld.ops = ops;
+  ld.pole_stride = I.pole_stride;
+  ld.leaves = leaves;
+  ld.npole = I.npole;
+  ld.nrhs = I.nrhs;
+  ld.q = I.q;
+  ld.row_groups = (I.q2 + 63) / 64;
+  ld.u = vec(I.levels[0].d_u);
+  ld.u_pole = I.levels[0].total_ext;
+  ld.w = w;
+  ld.w_pole = n_int;
+  ld.coef = coef;
+  ld.state = state;
+  ld.rhs_stride = 2 * n_int;
+  ld.n_int = (int)n_int;
+  ld.beta = I.beta;
+  ld.inv_tau = 1.0 / I.tau;
+  TIMED(HX_K_LEAF_DOWN, hx::launch_leaf_down_sum_mm<double>(ld, I.n_leaf, nt, s));
+  return HX_OK;
+}
+
+hx_status enqueue_single(hx_plan* plan, const Instance& I, double* state, hipStream_t s, Prof* prof) {
+  char* a = plan->arena;
+  const double2* ops = reinterpret_cast<const double2*>(a + I.d_ops);
+  double2* w = reinterpret_cast<double2*>(a + I.d_w);
+  const auto* leaves = reinterpret_cast<const LeafDesc*>(a + I.d_leaves);
+  const auto* coef = reinterpret_cast<const PoleCoef*>(a + I.d_coef);
+  const int* idx = reinterpret_cast<const int*>(a + I.d_idx);
+  const long long n_int = (long long)I.n_leaf * I.q2;
+  auto vec = [&](size_t off) { return reinterpret_cast<double2*>(a + off); };
+
+  hx::LeafUpArgs lu{};
+  lu.ops = ops;
+  lu.pole_stride = I.pole_stride;
+  lu.leaves = leaves;
+  lu.ncol = I.ncol;
+  lu.nrhs = I.nrhs;
+  lu.state = state;
+  lu.rhs_stride = 2 * n_int;
+  lu.n_int = (int)n_int;
+  lu.coef = coef;
+  lu.inv_tau = 1.0 / I.tau;
+  lu.inv_tau2 = 1.0 / (I.tau * I.tau);
+  lu.nrow = reinterpret_cast<const double*>(a + I.d_nrow);
+  lu.sx = 2.0 * I.mesh.nex / (I.mesh.x1 - I.mesh.x0);
+  lu.sy = 2.0 * I.mesh.ney / (I.mesh.y1 - I.mesh.y0);
+  lu.q = I.q;
+  lu.w = w;
+  lu.w_pole = n_int;
+  lu.h = vec(I.levels[0].d_h);
+  lu.h_pole = I.levels[0].total_ext;
+  TIMED(HX_K_LEAF_UP, hx::launch_leaf_up(lu, I.n_leaf, s));
+
+  const size_t nl = I.levels.size();
+  for (size_t l = 1; l < nl; ++l) {
+    const Level& L = I.levels[l];
+    hx::MergeArgs m{};
+    m.ops = ops;
+    m.pole_stride = I.pole_stride;
+    m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
+    m.idx = idx;
+    m.ncol = I.ncol;
+    m.nrhs = I.nrhs;
+    m.row_blocks = std::max(1, (L.max_ext + hx::kBlock - 1) / hx::kBlock);
+    m.child = vec(I.levels[l - 1].d_h);
+    m.child_pole = I.levels[l - 1].total_ext;
+    m.self = vec(L.d_h);
+    m.self_pole = L.total_ext;
+    m.g3 = vec(L.d_g3);
+    m.g3_pole = L.total_n3;
+    TIMED(HX_K_MERGE_UP, hx::launch_merge_up(m, (int)L.boxes.size(), L.max_n3, s));
+  }
+  for (size_t l = nl - 1; l >= 1; --l) {
+    const Level& L = I.levels[l];
+    hx::MergeArgs m{};
+    m.ops = ops;
+    m.pole_stride = I.pole_stride;
+    m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
+    m.idx = idx;
+    m.ncol = I.ncol;
+    m.nrhs = I.nrhs;
+    m.row_blocks = std::max(1, (L.max_n3 + hx::kBlock - 1) / hx::kBlock);
+    m.child = vec(I.levels[l - 1].d_u);
+    m.child_pole = I.levels[l - 1].total_ext;
+    m.self = vec(L.d_u);
+    m.self_pole = L.total_ext;
+    m.g3 = vec(L.d_g3);
+    m.g3_pole = L.total_n3;
+    TIMED(HX_K_MERGE_DOWN, hx::launch_merge_down(m, (int)L.boxes.size(), L.max_x, s));
+  }
+  hx::LeafDownArgs ld{};
+  ld.ops = ops;
+  ld.pole_stride = I.pole_stride;
+  ld.leaves = leaves;
+  ld.ncol = I.ncol;
+  ld.nrhs = I.nrhs;
+  ld.q = I.q;
+  ld.u = vec(I.levels[0].d_u);
+  ld.u_pole = I.levels[0].total_ext;
+  ld.w = w;
+  ld.w_pole = n_int;
+  TIMED(HX_K_LEAF_DOWN, hx::launch_leaf_down(ld, I.n_leaf, s));
+  return HX_OK;
+}
+
 hx_status enqueue_step(hx_plan* plan, double* const* states, hipStream_t s, Prof* prof = nullptr) {
   char* a = plan->arena;
   for (size_t k = 0; k < plan->inst.size(); ++k) {
     Instance& I = plan->inst[k];
-    const double2* ops = reinterpret_cast<const double2*>(a + I.d_ops);
-    double2* w = reinterpret_cast<double2*>(a + I.d_w);
-    const auto* leaves = reinterpret_cast<const LeafDesc*>(a + I.d_leaves);
-    const auto* coef = reinterpret_cast<const PoleCoef*>(a + I.d_coef);
-    const int* idx = reinterpret_cast<const int*>(a + I.d_idx);
+    if (batched(plan, I)) {  // pole sum fused into the leaf downward kernel
+      HX_TRY(enqueue_batched(plan, I, states[k], s, prof));
+      continue;
+    }
+    HX_TRY(enqueue_single(plan, I, states[k], s, prof));
     const long long n_int = (long long)I.n_leaf * I.q2;
-    auto lvl = [&](size_t l, size_t off) { return reinterpret_cast<double2*>(a + off); };
-
-    hx::LeafUpArgs lu{};
-    lu.ops = ops;
-    lu.pole_stride = I.pole_stride;
-    lu.leaves = leaves;
-    lu.ncol = I.ncol;
-    lu.nrhs = I.nrhs;
-    lu.state = states[k];
-    lu.rhs_stride = 2 * n_int;
-    lu.n_int = (int)n_int;
-    lu.coef = coef;
-    lu.inv_tau = 1.0 / I.tau;
-    lu.inv_tau2 = 1.0 / (I.tau * I.tau);
-    lu.nrow = reinterpret_cast<const double*>(a + I.d_nrow);
-    lu.sx = 2.0 * I.mesh.nex / (I.mesh.x1 - I.mesh.x0);
-    lu.sy = 2.0 * I.mesh.ney / (I.mesh.y1 - I.mesh.y0);
-    lu.q = I.q;
-    lu.w = w;
-    lu.w_col_stride = n_int;
-    lu.h = lvl(0, I.levels[0].d_h);
-    lu.h_col_stride = I.levels[0].total_ext;
-    TIMED(HX_K_LEAF_UP, hx::launch_leaf_up(lu, I.n_leaf, s));
-
-    const size_t nl = I.levels.size();
-    for (size_t l = 1; l < nl; ++l) {
-      const Level& L = I.levels[l];
-      hx::MergeArgs m{};
-      m.ops = ops;
-      m.pole_stride = I.pole_stride;
-      m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
-      m.idx = idx;
-      m.ncol = I.ncol;
-      m.nrhs = I.nrhs;
-      m.row_blocks = std::max(1, (L.max_ext + hx::kBlock - 1) / hx::kBlock);
-      m.child = lvl(l - 1, I.levels[l - 1].d_h);
-      m.child_col_stride = I.levels[l - 1].total_ext;
-      m.self = lvl(l, L.d_h);
-      m.self_col_stride = L.total_ext;
-      m.g3 = lvl(l, L.d_g3);
-      m.g3_col_stride = L.total_n3;
-      TIMED(HX_K_MERGE_UP, hx::launch_merge_up(m, (int)L.boxes.size(), L.max_n3, s));
-    }
-    for (size_t l = nl - 1; l >= 1; --l) {
-      const Level& L = I.levels[l];
-      hx::MergeArgs m{};
-      m.ops = ops;
-      m.pole_stride = I.pole_stride;
-      m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
-      m.idx = idx;
-      m.ncol = I.ncol;
-      m.nrhs = I.nrhs;
-      m.row_blocks = std::max(1, (L.max_n3 + hx::kBlock - 1) / hx::kBlock);
-      m.child = lvl(l - 1, I.levels[l - 1].d_u);
-      m.child_col_stride = I.levels[l - 1].total_ext;
-      m.self = lvl(l, L.d_u);
-      m.self_col_stride = L.total_ext;
-      m.g3 = lvl(l, L.d_g3);
-      m.g3_col_stride = L.total_n3;
-      TIMED(HX_K_MERGE_DOWN, hx::launch_merge_down(m, (int)L.boxes.size(), L.max_x, s));
-    }
-    hx::LeafDownArgs ld{};
-    ld.ops = ops;
-    ld.pole_stride = I.pole_stride;
-    ld.leaves = leaves;
-    ld.ncol = I.ncol;
-    ld.nrhs = I.nrhs;
-    ld.q = I.q;
-    ld.u = lvl(0, I.levels[0].d_u);
-    ld.u_col_stride = I.levels[0].total_ext;
-    ld.w = w;
-    ld.w_col_stride = n_int;
-    TIMED(HX_K_LEAF_DOWN, hx::launch_leaf_down(ld, I.n_leaf, s));
-
     hx::PoleSumArgs ps{};
-    ps.leaves = leaves;
+    ps.leaves = reinterpret_cast<const LeafDesc*>(a + I.d_leaves);
     ps.npole = I.npole;
     ps.nrhs = I.nrhs;
     ps.q = I.q;
-    ps.coef = coef;
-    ps.y = w;
-    ps.y_col_stride = n_int;
+    ps.coef = reinterpret_cast<const PoleCoef*>(a + I.d_coef);
+    ps.y = reinterpret_cast<const double2*>(a + I.d_w);
+    ps.y_pole = n_int;
     ps.state = states[k];
     ps.rhs_stride = 2 * n_int;
     ps.n_int = (int)n_int;

@@ -22,7 +22,7 @@ HX_OK, HX_EINVAL, HX_ENOMEM, HX_ESINGULAR = 0, -1, -2, -3
 HX_EUNSTABLE, HX_EDEVICE, HX_ESTATE, HX_ESTAGE = -4, -5, -6, -7
 HX_WAVE_DIRICHLET = 0
 HX_FP64 = 0
-HX_FLAG_ALLOW_UNSTABLE, HX_FLAG_NO_GRAPH, HX_FLAG_CHECK_STATE = 0x1, 0x2, 0x4
+HX_FLAG_ALLOW_UNSTABLE, HX_FLAG_NO_GRAPH, HX_FLAG_CHECK_STATE, HX_FLAG_UNBATCHED = 0x1, 0x2, 0x4, 0x8
 
 
 class hx_mesh(ctypes.Structure):

@@ -182,3 +182,26 @@ def test_eigenmode_at_full_size_100_steps():
     t = n * w.tau
     assert np.abs(got[0, 0] - np.cos(om * t) * phi).max() < 1e-8
     assert np.abs(got[0, 1] + om * np.sin(om * t) * phi).max() < 1e-8 * om
+
+
+# ---- many right-hand sides on the matrix cores ------------------------------------
+
+@pytest.mark.parametrize("nex,ney,p,nrhs", [(4, 4, 10, 2), (4, 2, 8, 16), (2, 4, 12, 17),
+                                            (4, 4, 10, 32), (2, 2, 16, 40), (2, 1, 18, 20),
+                                            (1, 1, 7, 3), (8, 8, 6, 33)])
+def test_batched_rhs_match_oracle(nex, ney, p, nrhs):
+    say(f"batched {nex}x{ney} p={p} nrhs={nrhs}")
+    w = make(nex, ney, p, n_rhs=nrhs)
+    rng = np.random.default_rng(nrhs)
+    w.v0 = 0.2 * rng.standard_normal(w.u0.shape) * w.u0      # nonzero velocities
+    got = gpu_run([w], 2)[0]
+    check(w, got, 2)
+
+
+def test_batched_equals_unbatched():
+    say("batched vs one pass per RHS, 4x4 p=10, 24 RHS")
+    from paper_1402_5168_amd import hpsexp
+    w = make(4, 4, 10, n_rhs=24)
+    a = gpu_run([w], 3)[0]
+    b = gpu_run([w], 3, flags=hpsexp.HX_FLAG_UNBATCHED)[0]
+    assert rel_err(a, b) <= 1e-13
