@@ -29,12 +29,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DOF·steps/s applying exp(τL), FP32-MFMA batched vs FP64, at rel err ≤1e-7"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6       # MI355X dense FP64 (vector and matrix)
+FP32_PEAK_TFLOPS = 157.3      # MI355X dense FP32 (vector and matrix)
 
 
 def interface_nodes(mesh) -> int:
     """Sum over elements of their non-boundary edge nodes."""
     sides = 2 * ((mesh.nex - 1) * mesh.ney + mesh.nex * (mesh.ney - 1))
     return sides * mesh.q
+
+
+def leaf_up_flops(mesh, npole: int, nrhs: int) -> float:
+    """W g for every element, folded pole and right-hand side: 8 flops per
+    complex multiply-add, q^4 of them per element and column."""
+    q2 = mesh.q * mesh.q
+    return 8.0 * mesh.n_el * q2 * q2 * npole * nrhs
 
 
 def algorithmic_bytes(mesh, npole: int, nrhs: int) -> dict:
@@ -99,6 +108,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="wave_32x32_p16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--nrhs", type=int, default=None,
+                    help="right-hand sides (default: the workload's own count)")
+    ap.add_argument("--unbatched", action="store_true",
+                    help="one pass per right-hand side (reference for the batching speedup)")
+    ap.add_argument("--precision", choices=["fp64", "fp32-refine"], default="fp64")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -112,10 +126,14 @@ def main():
     from workloads import configs
 
     rec = configs.RECIPES[args.workload]
-    w = configs.make(rec, n_rhs=None)
+    w = configs.make(rec, n_rhs=args.nrhs)
     m = w.mesh
     nrhs = w.u0.shape[0]
-    plan = hpsexp.Plan(device=0)
+    flags = hpsexp.HX_FLAG_UNBATCHED if args.unbatched else 0
+    fp32 = args.precision == "fp32-refine"
+    batched = fp32 or (nrhs > 1 and not args.unbatched)
+    plan = hpsexp.Plan(device=0, flags=flags,
+                       precision=hpsexp.HX_FP32_REFINE if fp32 else hpsexp.HX_FP64)
     plan.add(m.nex, m.ney, m.p, w.c2, w.tau, configs.DELTA, w.fit.alpha, w.fit.b, nrhs=nrhs)
     info = plan.query()
     plan.bind()
@@ -158,19 +176,30 @@ def main():
             entry["GBps"] = ab[name] / (avg * 1e-3) / 1e9
         kernels[name] = entry
     dom = kernels["k_leaf_up"]
-    roofline = {"bound": "hbm", "kernel": "k_leaf_up", "achieved": dom["GBps"],
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["GBps"] / HBM_PEAK_GBS,
-                "traffic": None,
-                "step_op_bytes_GBps": info["op_bytes_per_step"] / (ms_step * 1e-3) / 1e9}
+    if batched:
+        # each stored entry is used nrhs times: the sweeps are MFMA-bound
+        tf = leaf_up_flops(m, info["folded_poles"], nrhs) / (dom["ms_avg"] * 1e-3) / 1e12
+        dom["TFLOPs"] = tf
+        peak = FP32_PEAK_TFLOPS if fp32 else FP64_PEAK_TFLOPS
+        roofline = {"bound": "mfma", "kernel": "k_leaf_up", "achieved": tf,
+                    "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
+                    "traffic": None,
+                    "step_TFLOPs": info["flops_per_step"] / (ms_step * 1e-3) / 1e12}
+    else:
+        roofline = {"bound": "hbm", "kernel": "k_leaf_up", "achieved": dom["GBps"],
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["GBps"] / HBM_PEAK_GBS,
+                    "traffic": None,
+                    "step_op_bytes_GBps": info["op_bytes_per_step"] / (ms_step * 1e-3) / 1e9}
 
     out = {
         "metric": METRIC, "value": value, "unit": "DOF·steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if fp32 else "f64",
         "data": "synthetic",
         "config": {"workload": rec.name, "elements": f"{m.nex}x{m.ney}", "p": m.p,
                    "poles": rec.npoles, "folded_poles": info["folded_poles"], "nrhs": nrhs,
-                   "precision": "fp64", "tau": w.tau, "dof_state": info["dof_state"],
+                   "precision": args.precision, "batched_rhs": batched, "tau": w.tau, "dof_state": info["dof_state"],
                    "dof_nodes": info["dof_nodes"], "fit_X": info["fit_X"],
                    "max_abs_R": info["max_abs_R"],
                    "operator_GiB": info["operator_bytes"] / 2 ** 30},

@@ -66,8 +66,15 @@ typedef enum {
 /* Problem kinds. */
 #define HX_WAVE_DIRICHLET 0
 
-/* Arithmetic of the stored operators and sweeps. */
+/* Arithmetic of the stored operators and sweeps.
+ * HX_FP64: operators, sweeps and pole sum in FP64.
+ * HX_FP32_REFINE: the precision form.  Operators are built in FP64 and
+ *   stored in FP32; each step runs one FP32 sweep per pole, the FP64
+ *   residual of the collocation equations (interior rows and the flux
+ *   jumps across element edges), one FP32 correction sweep on that
+ *   residual, and the FP64 pole sum of the corrected solutions. */
 #define HX_FP64 0
+#define HX_FP32_REFINE 1
 
 /* Plan flags (hx_plan_create). */
 #define HX_FLAG_ALLOW_UNSTABLE 0x1u /* accept max|R(ix)| > 1 + 1e-6        */
@@ -125,7 +132,7 @@ typedef struct {
 } hx_info;
 
 /* Creates an empty plan for device `device` (a HIP ordinal).  precision:
- * HX_FP64.  flags: HX_FLAG_*.  Touches no device state.
+ * HX_FP64 or HX_FP32_REFINE.  flags: HX_FLAG_*.  Touches no device state.
  * HX_EINVAL on a bad precision or a null `out`. */
 hx_status hx_plan_create(hx_plan** out, int precision, int device, unsigned flags);
 
@@ -179,8 +186,9 @@ hx_status hx_step(hx_plan* plan, double* const* states, int n_steps, void* strea
 #define HX_K_MERGE_UP   1  /* merge upward pass, one launch per tree level       */
 #define HX_K_MERGE_DOWN 2  /* merge downward pass, one launch per tree level     */
 #define HX_K_LEAF_DOWN  3  /* element downward pass: w - S u_e                   */
-#define HX_K_POLE_SUM   4  /* FP64 pole sum and velocity post-map                 */
-#define HX_K_CLASSES    5
+#define HX_K_POLE_SUM   4  /* FP64 pole sum and velocity post-map (one RHS)       */
+#define HX_K_RESIDUAL   5  /* FP64 residual of the precision form                 */
+#define HX_K_CLASSES    6
 
 /* Diagnostic twin of hx_step: the same kernels, launched eagerly on
  * `stream` with a HIP event pair around every launch.  kernel_ms[c] and

@@ -49,10 +49,10 @@ __device__ __forceinline__ float2 ld_stream(const float2* p) {
 
 template <class T, int NT>
 struct Acc {
-  typename MM<T>::v4 rr[NT], ii[NT], ri[NT], ir[NT];
+  typename MM<T>::v4 re[NT], im[NT];
   __device__ void zero() {
     for (int t = 0; t < NT; ++t)
-      for (int v = 0; v < 4; ++v) rr[t][v] = ii[t][v] = ri[t][v] = ir[t][v] = T(0);
+      for (int v = 0; v < 4; ++v) re[t][v] = im[t][v] = T(0);
   }
 };
 
@@ -60,54 +60,71 @@ struct Acc {
 // A points at row 0 of the operator; rows >= nrows and columns >= kc give 0
 // (no load is issued for them).  Bs holds kc rows rounded up to a multiple
 // of 4, zero-padded, with row stride bst.
+//
+// A complex tile product is four real MFMAs into two accumulators:
+//   re += a.re b.re,  im += a.re b.im,  re += (-a.im) b.im,  im += a.im b.re,
+// ordered so that the two MFMAs feeding one accumulator are not adjacent.
+// Each k-step of 4 columns needs one complex A entry per lane from HBM; a
+// ring of PF registers keeps the next PF k-steps' loads in flight while
+// the current MFMAs run, so a wave does not stall on HBM latency.
+template <class T, int NT>
+__device__ __forceinline__ void mma_step(Acc<T, NT>& acc, const typename MM<T>::C a,
+                                         const typename MM<T>::C* __restrict__ Bk) {
+  using C = typename MM<T>::C;
+  const int i = threadIdx.x & 15;
+  const T nay = -a.y;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const C b = Bk[t * 16 + i];
+    acc.re[t] = MM<T>::mma(a.x, b.x, acc.re[t]);
+    acc.im[t] = MM<T>::mma(a.x, b.y, acc.im[t]);
+    acc.re[t] = MM<T>::mma(nay, b.y, acc.re[t]);
+    acc.im[t] = MM<T>::mma(a.y, b.x, acc.im[t]);
+  }
+}
+
 template <class T, int NT>
 __device__ __forceinline__ void mm_chunk(Acc<T, NT>& acc, const typename MM<T>::C* __restrict__ A,
                                          long long lda, int row0, int nrows, int k_lo, int kc,
                                          const typename MM<T>::C* __restrict__ Bs, int bst) {
   using C = typename MM<T>::C;
+  constexpr int PF = 8;
   const int lane = threadIdx.x & 63;
   const int i = lane & 15, kk = lane >> 4;
   const bool rv = row0 + i < nrows;
-  const C* Ar = A + row0 + i + (long long)k_lo * lda;
-  const int kcp = (kc + 3) & ~3;
-  int k4 = 0;
-  for (; k4 + 8 <= kcp; k4 += 8) {
-    const int k0 = k4 + kk, k1 = k4 + 4 + kk;
-    C a0, a1;
-    a0.x = a0.y = a1.x = a1.y = T(0);
-    if (rv && k0 < kc) a0 = ld_stream(Ar + (long long)k0 * lda);
-    if (rv && k1 < kc) a1 = ld_stream(Ar + (long long)k1 * lda);
+  const C* ap = A + row0 + i + (long long)(k_lo + kk) * lda;   // next load
+  const long long step = 4 * lda;
+  const int nsteps = (kc + 3) >> 2;
+  int kn = kk;                                                // column of the next load
+  C ring[PF];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const C b0 = Bs[k0 * bst + t * 16 + i];
-      acc.rr[t] = MM<T>::mma(a0.x, b0.x, acc.rr[t]);
-      acc.ii[t] = MM<T>::mma(a0.y, b0.y, acc.ii[t]);
-      acc.ri[t] = MM<T>::mma(a0.x, b0.y, acc.ri[t]);
-      acc.ir[t] = MM<T>::mma(a0.y, b0.x, acc.ir[t]);
-    }
+  for (int u = 0; u < PF; ++u) {
+    ring[u].x = ring[u].y = T(0);
+    if (rv && kn < kc) ring[u] = ld_stream(ap);
+    ap += step;
+    kn += 4;
+  }
+  const C* Bk = Bs + kk * bst;
+  const int bstep = 4 * bst;
+  int s0 = 0;
+  for (; s0 + PF <= nsteps; s0 += PF) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const C b1 = Bs[k1 * bst + t * 16 + i];
-      acc.rr[t] = MM<T>::mma(a1.x, b1.x, acc.rr[t]);
-      acc.ii[t] = MM<T>::mma(a1.y, b1.y, acc.ii[t]);
-      acc.ri[t] = MM<T>::mma(a1.x, b1.y, acc.ri[t]);
-      acc.ir[t] = MM<T>::mma(a1.y, b1.x, acc.ir[t]);
+    for (int u = 0; u < PF; ++u) {
+      const C a = ring[u];
+      ring[u].x = ring[u].y = T(0);
+      if (rv && kn < kc) ring[u] = ld_stream(ap);
+      ap += step;
+      kn += 4;
+      mma_step<T, NT>(acc, a, Bk);
+      Bk += bstep;
     }
   }
-  for (; k4 < kcp; k4 += 4) {
-    const int k = k4 + kk;
-    C a;
-    a.x = a.y = T(0);
-    if (rv && k < kc) a = ld_stream(Ar + (long long)k * lda);
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const C b = Bs[k * bst + t * 16 + i];
-      acc.rr[t] = MM<T>::mma(a.x, b.x, acc.rr[t]);
-      acc.ii[t] = MM<T>::mma(a.y, b.y, acc.ii[t]);
-      acc.ri[t] = MM<T>::mma(a.x, b.y, acc.ri[t]);
-      acc.ir[t] = MM<T>::mma(a.y, b.x, acc.ir[t]);
+  for (int u = 0; u < PF; ++u)
+    if (s0 + u < nsteps) {
+      mma_step<T, NT>(acc, ring[u], Bk);
+      Bk += bstep;
     }
-  }
 }
 
 // Visit the wave's results: f(row, j, value) for row < nrows, j < RT.
@@ -122,8 +139,8 @@ __device__ __forceinline__ void mm_emit(const Acc<T, NT>& acc, int row0, int nro
       const int row = row0 + MM<T>::row(lane, v);
       if (row < nrows) {
         C c;
-        c.x = acc.rr[t][v] - acc.ii[t][v];
-        c.y = acc.ri[t][v] + acc.ir[t][v];
+        c.x = acc.re[t][v];
+        c.y = acc.im[t][v];
         f(row, t * 16 + (lane & 15), c);
       }
     }
@@ -153,10 +170,14 @@ __global__ __launch_bounds__(kBlock) void k_leaf_up_mm(MmLeafUpArgs<T> a) {
     C g;
     g.x = g.y = T(0);
     if (k < q2 && rhs < r) {
-      const double* u0 = a.state + rhs * a.rhs_stride + (long long)L.elem * q2;
-      const double uu = u0[k], vv = u0[a.n_int + k];
-      g.x = T(fma(al.x * a.inv_tau2, uu, vv * a.inv_tau));
-      g.y = T(al.y * a.inv_tau2 * uu);
+      if (a.gin) {
+        g = a.gin[((long long)pole * a.w_pole + (long long)leaf * q2 + k) * r + rhs];
+      } else {
+        const double* u0 = a.state + rhs * a.rhs_stride + (long long)L.elem * q2;
+        const double uu = u0[k], vv = u0[a.n_int + k];
+        g.x = T(fma(al.x * a.inv_tau2, uu, vv * a.inv_tau));
+        g.y = T(al.y * a.inv_tau2 * uu);
+      }
     }
     gs[k * BST + j] = g;
   }
@@ -239,6 +260,16 @@ __global__ __launch_bounds__(kBlock) void k_merge_up_mm(MmMergeArgs<T> a) {
         const C y = hc[(long long)(B.b_vec + i3b[k0 + k]) * r + rhs];
         v.x = x.x + y.x;
         v.y = x.y + y.y;
+        if (a.dn) {
+          // flux rows of the correction: du/dn(a) + du/dn(b) = -(dn_a + dn_b),
+          // which enters as g3 = h3a + h3b + dn_a + dn_b
+          const int* ja = a.idx + B.j_off;
+          const double2* dp = a.dn + (long long)pole * a.dn_pole * r;
+          const double2 da = dp[(long long)ja[k0 + k] * r + rhs];
+          const double2 db = dp[(long long)ja[n3 + k0 + k] * r + rhs];
+          v.x += T(da.x + db.x);
+          v.y += T(da.y + db.y);
+        }
         if (rg == 0) g3[(long long)(k0 + k) * r + rhs] = v;
       }
       Bs[k * BST + j] = v;
@@ -360,14 +391,14 @@ __global__ __launch_bounds__(kBlock) void k_leaf_down_mm(MmLeafDownArgs<T> a) {
   acc.zero();
   if (e > 0) mm_chunk<T, NT>(acc, S, q2, row0, q2, 0, e, Bs, BST);
   C* w = a.w + ((long long)pole * a.w_pole + (long long)leaf * q2) * r;
+  C* yo = a.y0 ? a.y0 + ((long long)pole * a.w_pole + (long long)leaf * q2) * r : w;
   mm_emit<T, NT>(acc, row0, q2, [&](int row, int j, C c) {
     const int rhs = rt * RT + j;
     if (rhs >= r) return;
-    C& y = w[(long long)row * r + rhs];
-    C o = y;
+    C o = w[(long long)row * r + rhs];
     o.x -= c.x;
     o.y -= c.y;
-    y = o;
+    yo[(long long)row * r + rhs] = o;
   });
 }
 
@@ -410,6 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_down_sum_mm(MmLeafDownArgs<T> a
       acc.zero();
       if (e > 0) mm_chunk<T, NT>(acc, S, q2, row0, q2, 0, e, Bs, BST);
       const C* w = a.w + ((long long)pole * a.w_pole + (long long)leaf * q2) * r;
+      const C* y0 = a.y0 ? a.y0 + ((long long)pole * a.w_pole + (long long)leaf * q2) * r : nullptr;
       const PoleCoef pc = a.coef[pole];
 #pragma unroll
       for (int t = 0; t < NT; ++t)
@@ -419,8 +451,13 @@ __global__ __launch_bounds__(kBlock) void k_leaf_down_sum_mm(MmLeafDownArgs<T> a
           const int rhs = rt * RT + t * 16 + (lane & 15);
           if (row < q2 && rhs < r) {
             const C wv = w[(long long)row * r + rhs];
-            const double yr = double(wv.x) - double(acc.rr[t][v] - acc.ii[t][v]);
-            const double yi = double(wv.y) - double(acc.ri[t][v] + acc.ir[t][v]);
+            double yr = double(wv.x) - double(acc.re[t][v]);
+            double yi = double(wv.y) - double(acc.im[t][v]);
+            if (y0) {  // corrected solution of the precision form
+              const C y0v = y0[(long long)row * r + rhs];
+              yr += double(y0v.x);
+              yi += double(y0v.y);
+            }
             su[t][v] = fma(pc.cu.x, yr, fma(-pc.cu.y, yi, su[t][v]));
             sv[t][v] = fma(pc.cv.x, yr, fma(-pc.cv.y, yi, sv[t][v]));
           }
@@ -514,6 +551,11 @@ hipError_t launch_leaf_down_sum_mm(const MmLeafDownArgs<T>& a, int n_leaf, int n
 }
 
 template hipError_t launch_leaf_down_sum_mm<double>(const MmLeafDownArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_leaf_down_sum_mm<float>(const MmLeafDownArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_leaf_up_mm<float>(const MmLeafUpArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_merge_up_mm<float>(const MmMergeArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_merge_down_mm<float>(const MmMergeArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_leaf_down_mm<float>(const MmLeafDownArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_leaf_up_mm<double>(const MmLeafUpArgs<double>&, int, int, hipStream_t);
 template hipError_t launch_merge_up_mm<double>(const MmMergeArgs<double>&, int, int, hipStream_t);
 template hipError_t launch_merge_down_mm<double>(const MmMergeArgs<double>&, int, int, hipStream_t);

@@ -157,6 +157,24 @@ __global__ __launch_bounds__(kBlock) void k_nonfinite(const double* __restrict__
   if (bad) flag[0] = 1;
 }
 
+// FP64 -> FP32 copy of a chunk of operators (precision form).
+__global__ __launch_bounds__(kBlock) void k_pack_f32(const double2* __restrict__ src,
+                                                     float2* __restrict__ dst, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double2 v = src[i];
+    dst[i] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
+hipError_t launch_pack_f32(const double2* src, float2* dst, long long n, hipStream_t s) {
+  long long blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_pack_f32, dim3((unsigned)blocks), dim3(kBlock), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_leaf_assemble(const LeafAssembleArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_leaf_assemble, dim3(a.n_leaf * a.chunk), dim3(kBlock), 0, s, a);
   return hipGetLastError();

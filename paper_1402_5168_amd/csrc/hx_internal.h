@@ -45,6 +45,8 @@ struct BoxDesc {
   int n1, n2, n3;    // exterior-from-a, exterior-from-b, interface sizes
   int idx_off;       // int32 maps: idx1[n1] idx2[n2] idx3a[n3] idx3b[n3]
   int a_box, b_box;  // children's indices in the level below
+  int j_off;         // int32 maps ja[n3] jb[n3]: the two element-edge slots
+                     // (level-0 vector positions) of each interface node
 };
 
 struct PoleCoef {

@@ -94,6 +94,9 @@ struct MmLeafUpArgs {
   long long w_pole;
   typename Cplx<T>::type* h;   // [pole][sum of e][rhs]
   long long h_pole;
+  // precision form, correction sweep: right-hand side taken from the
+  // residual [pole][leaf][q*q][rhs] instead of the state (null: state)
+  const typename Cplx<T>::type* gin;
 };
 
 template <class T>
@@ -109,6 +112,11 @@ struct MmMergeArgs {
   long long self_pole;
   typename Cplx<T>::type* g3;
   long long g3_pole;
+  // precision form, correction sweep: flux-jump residual from the element
+  // normal derivatives dn [pole][sum of e][rhs], FP64 because the two
+  // elements' values nearly cancel (null: none)
+  const double2* dn;
+  long long dn_pole;
 };
 
 template <class T>
@@ -127,7 +135,30 @@ struct MmLeafDownArgs {
   long long rhs_stride;
   int n_int;
   double beta, inv_tau;
+  // precision form: y0 = first-sweep solution; the unfused variant writes
+  // y = w - S u_e there, the fused variant sums y0 + w - S u_e (null: unused)
+  typename Cplx<T>::type* y0;
 };
+
+// FP64 residual of the collocation equations for the precision form.
+struct ResidualArgs {
+  const LeafDesc* leaves;
+  int npole, nrhs, p, q;
+  const double* c2;          // [elem][p*p]
+  const double* D;           // p x p row-major
+  double sx, sy, tau;
+  const PoleCoef* coef;
+  const double* state;
+  long long rhs_stride;
+  int n_int;
+  const float2* y0;          // first-sweep interior solution [pole][leaf][q*q][rhs]
+  long long w_pole;
+  const float2* ue;          // first-sweep edge values (level-0 u) [pole][sum e][rhs]
+  long long e_pole;
+  float2* gres;              // residual of the interior rows, same layout as y0
+  double2* dn;               // outward normal derivative at the edge slots, as ue (FP64)
+};
+hipError_t launch_residual(const ResidualArgs& a, int n_leaf, hipStream_t s);
 
 // nt = right-hand-side tiles of 16 per block (1 or 2)
 template <class T> hipError_t launch_leaf_up_mm(const MmLeafUpArgs<T>& a, int n_leaf, int nt, hipStream_t s);
@@ -186,5 +217,6 @@ hipError_t launch_leaf_assemble(const LeafAssembleArgs& a, hipStream_t s);
 hipError_t launch_leaf_dtn(const LeafDtnArgs& a, hipStream_t s);
 hipError_t launch_merge_gather(const MergeGatherArgs& a, int n_box, hipStream_t s);
 hipError_t launch_nonfinite_check(const double* x, long long n, int* flag, hipStream_t s);
+hipError_t launch_pack_f32(const double2* src, float2* dst, long long n, hipStream_t s);
 
 }  // namespace hx

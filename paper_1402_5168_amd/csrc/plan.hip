@@ -106,14 +106,18 @@ struct Instance {
   long long pole_stride = 0;                // complex elements per pole block
   long long leaf_ops = 0, merge_ops = 0;    // complex elements per pole
   double max_abs_R = 0.0, fit_X = 0.0, sum_abs_b = 0.0;
+  bool fp32 = false;                        // precision form: FP32 operators and sweeps
   // arena layout (byte offsets)
   size_t d_ops = 0, d_w = 0, d_leaves = 0, d_idx = 0, d_coef = 0, d_nrow = 0, end = 0;
+  size_t d_y0 = 0, d_gres = 0, d_dn = 0, d_c2 = 0, d_D = 0;  // precision form only
+  size_t cbytes() const { return fp32 ? sizeof(float2) : sizeof(double2); }
 };
 
 }  // namespace
 
 struct hx_plan {
   int device = 0;
+  int precision = HX_FP64;
   unsigned flags = 0;
   std::vector<Instance> inst;
   char* arena = nullptr;
@@ -129,6 +133,13 @@ struct hx_plan {
 };
 
 namespace {
+
+// Many right-hand sides go through the matrix-core kernels unless the plan
+// asks for one pass per right-hand side (the unbatched reference); the
+// precision form always does.
+bool batched(const hx_plan* plan, const Instance& I) {
+  return I.fp32 || (I.nrhs > 1 && !(plan->flags & HX_FLAG_UNBATCHED));
+}
 
 // ---- rational function checks (eqs. RM_prop1 and RM_prop2) ----------------
 
@@ -184,6 +195,8 @@ void build_tree(Instance& I) {
   I.levels.emplace_back();
   long long op = 0;
   int vec = 0;
+  // the two element-edge slots (level-0 vector positions) of each interface node
+  std::vector<int> slot_a(std::max(n_nodes, 1), -1), slot_b(std::max(n_nodes, 1), -1);
   for (int ey = 0; ey < ney; ++ey)
     for (int ex = 0; ex < nex; ++ex) {
       TBox b{ex, ey, 1, 1, {}};
@@ -192,6 +205,10 @@ void build_tree(Instance& I) {
       if (ex < nex - 1) { mask |= 2; for (int t = 0; t < q; ++t) b.ext.push_back(vnode(ex, ey, t)); }
       if (ey > 0) { mask |= 4; for (int t = 0; t < q; ++t) b.ext.push_back(hnode(ex, ey - 1, t)); }
       if (ey < ney - 1) { mask |= 8; for (int t = 0; t < q; ++t) b.ext.push_back(hnode(ex, ey, t)); }
+      for (size_t k = 0; k < b.ext.size(); ++k) {
+        int& sl = slot_a[b.ext[k]] < 0 ? slot_a[b.ext[k]] : slot_b[b.ext[k]];
+        sl = vec + (int)k;
+      }
       LeafDesc L{};
       L.op_off = op;
       L.vec_off = vec;
@@ -263,6 +280,9 @@ void build_tree(Instance& I) {
         I.idx.insert(I.idx.end(), i2.begin(), i2.end());
         I.idx.insert(I.idx.end(), i3a.begin(), i3a.end());
         I.idx.insert(I.idx.end(), i3b.begin(), i3b.end());
+        D.j_off = (int)I.idx.size();
+        for (int id : s3) I.idx.push_back(slot_a[id]);
+        for (int id : s3) I.idx.push_back(slot_b[id]);
         const long long ext = D.n1 + D.n2;
         D.op_off = op;
         op += align_up((size_t)(D.n3 * (ext + D.n3) + ext * D.n3), 8);
@@ -298,14 +318,22 @@ void layout_arena(hx_plan* plan) {
   };
   plan->d_flag_off = take(sizeof(int));
   for (auto& I : plan->inst) {
-    I.d_ops = take(sizeof(double2) * (size_t)I.pole_stride * I.npole);
-    I.d_w = take(sizeof(double2) * (size_t)I.ncol * I.n_leaf * I.q2);
+    const size_t cb = I.cbytes();
+    I.d_ops = take(cb * (size_t)I.pole_stride * I.npole);
+    I.d_w = take(cb * (size_t)I.ncol * I.n_leaf * I.q2);
     for (size_t l = 0; l < I.levels.size(); ++l) {
       Level& L = I.levels[l];
-      L.d_h = take(sizeof(double2) * (size_t)I.ncol * L.total_ext);
-      L.d_u = take(sizeof(double2) * (size_t)I.ncol * L.total_ext);
-      L.d_g3 = take(sizeof(double2) * (size_t)I.ncol * L.total_n3);
+      L.d_h = take(cb * (size_t)I.ncol * L.total_ext);
+      L.d_u = take(cb * (size_t)I.ncol * L.total_ext);
+      L.d_g3 = take(cb * (size_t)I.ncol * L.total_n3);
       L.d_boxes = take(sizeof(BoxDesc) * L.boxes.size());
+    }
+    if (I.fp32) {
+      I.d_y0 = take(cb * (size_t)I.ncol * I.n_leaf * I.q2);
+      I.d_gres = take(cb * (size_t)I.ncol * I.n_leaf * I.q2);
+      I.d_dn = take(sizeof(double2) * (size_t)I.ncol * I.levels[0].total_ext);
+      I.d_c2 = take(sizeof(double) * I.c2.size());
+      I.d_D = take(sizeof(double) * I.mesh.p * I.mesh.p);
     }
     I.d_leaves = take(sizeof(LeafDesc) * I.leaves.size());
     I.d_idx = take(sizeof(int) * I.idx.size());
@@ -319,7 +347,7 @@ void layout_arena(hx_plan* plan) {
 // Build workspace layout for a chunk of `ch` poles of one instance.
 struct WsLayout {
   size_t A = 0, T0 = 0, T1 = 0, ipiv = 0, info = 0, ptr = 0, c2 = 0, D = 0, sigma = 0,
-         toff = 0, total = 0;
+         toff = 0, ops64 = 0, total = 0;
   long long sizeA = 0, sizeT = 0, sizeIpiv = 0, sizeInfo = 0, sizePtr = 0, n_off = 0;
 };
 
@@ -364,6 +392,7 @@ WsLayout ws_layout(const Instance& I, int ch) {
   w.D = take(sizeof(double) * I.mesh.p * I.mesh.p);
   w.sigma = take(sizeof(double2) * ch);
   w.toff = take(sizeof(long long) * 4 * (size_t)std::max<long long>(w.n_off, 1));
+  if (I.fp32) w.ops64 = take(sizeof(double2) * (size_t)I.pole_stride * ch);
   w.total = off;
   return w;
 }
@@ -443,7 +472,10 @@ hx_status check_info(const Build& B, const WsLayout& W, long long n, const char*
 }
 
 hx_status build_chunk(Build& B, Instance& I, const WsLayout& W, int p0, int ch) {
-  double2* ops = reinterpret_cast<double2*>(B.plan->arena + I.d_ops) + (long long)p0 * I.pole_stride;
+  // FP64 operators of this chunk: straight into the arena, or into the
+  // workspace first when the arena holds FP32 operators
+  double2* ops = I.fp32 ? wsp<double2>(B, W.ops64)
+                        : reinterpret_cast<double2*>(B.plan->arena + I.d_ops) + (long long)p0 * I.pole_stride;
   const int q2 = I.q2;
   const double sx = 2.0 * I.mesh.nex / (I.mesh.x1 - I.mesh.x0);
   const double sy = 2.0 * I.mesh.ney / (I.mesh.y1 - I.mesh.y0);
@@ -623,6 +655,10 @@ hx_status build_chunk(Build& B, Instance& I, const WsLayout& W, int p0, int ch) 
     std::swap(Tc, Tp);
     child_off = poff;
   }
+  if (I.fp32) {
+    float2* dst = reinterpret_cast<float2*>(B.plan->arena + I.d_ops) + (long long)p0 * I.pole_stride;
+    HIP_OK(hx::launch_pack_f32(ops, dst, (long long)ch * I.pole_stride, B.s));
+  }
   return HX_OK;
 }
 
@@ -654,12 +690,14 @@ hx_status hx_plan_create(hx_plan** out, int precision, int device, unsigned flag
   g_last_error.clear();
   if (!out) return fail(HX_EINVAL, "out is null");
   *out = nullptr;
-  if (precision != HX_FP64) return fail(HX_EINVAL, "unsupported precision %d", precision);
+  if (precision != HX_FP64 && precision != HX_FP32_REFINE)
+    return fail(HX_EINVAL, "unsupported precision %d", precision);
   if (device < 0) return fail(HX_EINVAL, "device %d", device);
   if (flags & ~(HX_FLAG_ALLOW_UNSTABLE | HX_FLAG_NO_GRAPH | HX_FLAG_CHECK_STATE | HX_FLAG_UNBATCHED))
     return fail(HX_EINVAL, "unknown flags 0x%x", flags);
   hx_plan* p = new hx_plan;
   p->device = device;
+  p->precision = precision;
   p->flags = flags;
   *out = p;
   return HX_OK;
@@ -682,6 +720,7 @@ hx_status hx_plan_add(hx_plan* plan, const hx_mesh* mesh, const hx_coeffs* coeff
   I.ncol = I.npole * nrhs;
   I.tau = tau;
   I.delta = delta;
+  I.fp32 = plan->precision == HX_FP32_REFINE;
   I.c2.assign(coeffs->c2, coeffs->c2 + (size_t)I.n_leaf * mesh->p * mesh->p);
   for (int k = 0; k < rational->npoles; ++k) {
     I.alpha.emplace_back(rational->alpha[2 * k], rational->alpha[2 * k + 1]);
@@ -728,7 +767,7 @@ hx_status hx_plan_query(const hx_plan* plan, hx_info* info) {
   r.fit_X = 1e300;
   size_t wmax = 0, wmin = 0;
   for (auto& I : plan->inst) {
-    r.operator_bytes += sizeof(double2) * (size_t)(I.leaf_ops + I.merge_ops) * I.npole;
+    r.operator_bytes += I.cbytes() * (size_t)(I.leaf_ops + I.merge_ops) * I.npole;
     r.dof_state += 2LL * I.n_leaf * I.q2 * I.nrhs;
     r.dof_nodes += 2LL * I.n_leaf * I.mesh.p * I.mesh.p * I.nrhs;
     r.folded_poles += I.npole;
@@ -740,8 +779,12 @@ hx_status hx_plan_query(const hx_plan* plan, hx_info* info) {
         const long long ext = B.n1 + B.n2;
         entries += (long long)B.n3 * (ext + B.n3) + ext * B.n3;
       }
-    r.op_bytes_per_step += 16.0 * (double)entries * I.npole * I.nrhs;
-    r.flops_per_step += 8.0 * (double)entries * I.npole * I.nrhs;
+    // one sweep (FP64) or two (precision form) per step; batched right-hand
+    // sides share each operator read
+    const double sweeps = I.fp32 ? 2.0 : 1.0;
+    const double reads = batched(plan, I) ? 1.0 : (double)I.nrhs;
+    r.op_bytes_per_step += sweeps * (double)I.cbytes() * (double)entries * I.npole * reads;
+    r.flops_per_step += sweeps * 8.0 * (double)entries * I.npole * I.nrhs;
     r.max_abs_R = std::max(r.max_abs_R, I.max_abs_R);
     r.fit_X = std::min(r.fit_X, I.fit_X);
     r.sum_abs_b = std::max(r.sum_abs_b, I.sum_abs_b);
@@ -775,6 +818,11 @@ hx_status hx_plan_bind(hx_plan* plan, void* arena, size_t arena_bytes) {
       HIP_OK(hipMemcpy(a + I.d_idx, I.idx.data(), sizeof(int) * I.idx.size(), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(a + I.d_coef, I.coef.data(), sizeof(PoleCoef) * I.coef.size(), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(a + I.d_nrow, I.nrow.data(), sizeof(double) * I.nrow.size(), hipMemcpyHostToDevice));
+    if (I.fp32) {
+      const std::vector<double> D = cheb_diff(I.mesh.p);
+      HIP_OK(hipMemcpy(a + I.d_c2, I.c2.data(), sizeof(double) * I.c2.size(), hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(a + I.d_D, D.data(), sizeof(double) * D.size(), hipMemcpyHostToDevice));
+    }
     for (auto& L : I.levels)
       if (!L.boxes.empty())
         HIP_OK(hipMemcpy(a + L.d_boxes, L.boxes.data(), sizeof(BoxDesc) * L.boxes.size(), hipMemcpyHostToDevice));
@@ -854,11 +902,6 @@ struct Prof {
     if (prof) HX_TRY(prof->end());              \
   } while (0)
 
-// Many right-hand sides go through the matrix-core kernels unless the plan
-// asks for one launch per right-hand side (the unbatched reference).
-bool batched(const hx_plan* plan, const Instance& I) {
-  return I.nrhs > 1 && !(plan->flags & HX_FLAG_UNBATCHED);
-}
 
 hx_status enqueue_batched(hx_plan* plan, const Instance& I, double* state, hipStream_t s, Prof* prof) {
   char* a = plan->arena;
@@ -952,6 +995,137 @@ hx_status enqueue_batched(hx_plan* plan, const Instance& I, double* state, hipSt
   return HX_OK;
 }
 
+// Precision form: FP32 sweep, FP64 residual, FP32 correction sweep, FP64
+// pole sum of the corrected solutions.
+hx_status enqueue_refine(hx_plan* plan, const Instance& I, double* state, hipStream_t s, Prof* prof) {
+  char* a = plan->arena;
+  const float2* ops = reinterpret_cast<const float2*>(a + I.d_ops);
+  float2* w = reinterpret_cast<float2*>(a + I.d_w);
+  float2* y0 = reinterpret_cast<float2*>(a + I.d_y0);
+  float2* gres = reinterpret_cast<float2*>(a + I.d_gres);
+  double2* dn = reinterpret_cast<double2*>(a + I.d_dn);
+  const auto* leaves = reinterpret_cast<const LeafDesc*>(a + I.d_leaves);
+  const auto* coef = reinterpret_cast<const PoleCoef*>(a + I.d_coef);
+  const int* idx = reinterpret_cast<const int*>(a + I.d_idx);
+  const long long n_int = (long long)I.n_leaf * I.q2;
+  auto vec = [&](size_t off) { return reinterpret_cast<float2*>(a + off); };
+  const int nt = I.nrhs > 16 ? 2 : 1;
+  const double sx = 2.0 * I.mesh.nex / (I.mesh.x1 - I.mesh.x0);
+  const double sy = 2.0 * I.mesh.ney / (I.mesh.y1 - I.mesh.y0);
+
+  for (int pass = 0; pass < 2; ++pass) {
+    hx::MmLeafUpArgs<float> lu{};
+    lu.ops = ops;
+    lu.pole_stride = I.pole_stride;
+    lu.leaves = leaves;
+    lu.npole = I.npole;
+    lu.nrhs = I.nrhs;
+    lu.q = I.q;
+    lu.state = state;
+    lu.rhs_stride = 2 * n_int;
+    lu.n_int = (int)n_int;
+    lu.coef = coef;
+    lu.inv_tau = 1.0 / I.tau;
+    lu.inv_tau2 = 1.0 / (I.tau * I.tau);
+    lu.nrow = reinterpret_cast<const double*>(a + I.d_nrow);
+    lu.sx = sx;
+    lu.sy = sy;
+    lu.w = w;
+    lu.w_pole = n_int;
+    lu.h = vec(I.levels[0].d_h);
+    lu.h_pole = I.levels[0].total_ext;
+    lu.gin = pass ? gres : nullptr;
+    TIMED(HX_K_LEAF_UP, hx::launch_leaf_up_mm<float>(lu, I.n_leaf, nt, s));
+
+    const size_t nl = I.levels.size();
+    for (size_t l = 1; l < nl; ++l) {
+      const Level& L = I.levels[l];
+      hx::MmMergeArgs<float> m{};
+      m.ops = ops;
+      m.pole_stride = I.pole_stride;
+      m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
+      m.idx = idx;
+      m.npole = I.npole;
+      m.nrhs = I.nrhs;
+      m.row_groups = std::max(1, (L.max_ext + 63) / 64);
+      m.child = vec(I.levels[l - 1].d_h);
+      m.child_pole = I.levels[l - 1].total_ext;
+      m.self = vec(L.d_h);
+      m.self_pole = L.total_ext;
+      m.g3 = vec(L.d_g3);
+      m.g3_pole = L.total_n3;
+      m.dn = pass ? dn : nullptr;
+      m.dn_pole = I.levels[0].total_ext;
+      TIMED(HX_K_MERGE_UP, hx::launch_merge_up_mm<float>(m, (int)L.boxes.size(), nt, s));
+    }
+    for (size_t l = nl - 1; l >= 1; --l) {
+      const Level& L = I.levels[l];
+      hx::MmMergeArgs<float> m{};
+      m.ops = ops;
+      m.pole_stride = I.pole_stride;
+      m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
+      m.idx = idx;
+      m.npole = I.npole;
+      m.nrhs = I.nrhs;
+      m.row_groups = std::max(1, (L.max_n3 + 63) / 64);
+      m.child = vec(I.levels[l - 1].d_u);
+      m.child_pole = I.levels[l - 1].total_ext;
+      m.self = vec(L.d_u);
+      m.self_pole = L.total_ext;
+      m.g3 = vec(L.d_g3);
+      m.g3_pole = L.total_n3;
+      TIMED(HX_K_MERGE_DOWN, hx::launch_merge_down_mm<float>(m, (int)L.boxes.size(), nt, s));
+    }
+    hx::MmLeafDownArgs<float> ld{};
+    ld.ops = ops;
+    ld.pole_stride = I.pole_stride;
+    ld.leaves = leaves;
+    ld.npole = I.npole;
+    ld.nrhs = I.nrhs;
+    ld.q = I.q;
+    ld.row_groups = (I.q2 + 63) / 64;
+    ld.u = vec(I.levels[0].d_u);
+    ld.u_pole = I.levels[0].total_ext;
+    ld.w = w;
+    ld.w_pole = n_int;
+    ld.coef = coef;
+    ld.state = state;
+    ld.rhs_stride = 2 * n_int;
+    ld.n_int = (int)n_int;
+    ld.beta = I.beta;
+    ld.inv_tau = 1.0 / I.tau;
+    ld.y0 = y0;
+    if (pass == 0) {
+      TIMED(HX_K_LEAF_DOWN, hx::launch_leaf_down_mm<float>(ld, I.n_leaf, nt, s));
+      hx::ResidualArgs ra{};
+      ra.leaves = leaves;
+      ra.npole = I.npole;
+      ra.nrhs = I.nrhs;
+      ra.p = I.mesh.p;
+      ra.q = I.q;
+      ra.c2 = reinterpret_cast<const double*>(a + I.d_c2);
+      ra.D = reinterpret_cast<const double*>(a + I.d_D);
+      ra.sx = sx;
+      ra.sy = sy;
+      ra.tau = I.tau;
+      ra.coef = coef;
+      ra.state = state;
+      ra.rhs_stride = 2 * n_int;
+      ra.n_int = (int)n_int;
+      ra.y0 = y0;
+      ra.w_pole = n_int;
+      ra.ue = vec(I.levels[0].d_u);
+      ra.e_pole = I.levels[0].total_ext;
+      ra.gres = gres;
+      ra.dn = dn;
+      TIMED(HX_K_RESIDUAL, hx::launch_residual(ra, I.n_leaf, s));
+    } else {
+      TIMED(HX_K_LEAF_DOWN, hx::launch_leaf_down_sum_mm<float>(ld, I.n_leaf, nt, s));
+    }
+  }
+  return HX_OK;
+}
+
 hx_status enqueue_single(hx_plan* plan, const Instance& I, double* state, hipStream_t s, Prof* prof) {
   char* a = plan->arena;
   const double2* ops = reinterpret_cast<const double2*>(a + I.d_ops);
@@ -1040,6 +1214,10 @@ hx_status enqueue_step(hx_plan* plan, double* const* states, hipStream_t s, Prof
   char* a = plan->arena;
   for (size_t k = 0; k < plan->inst.size(); ++k) {
     Instance& I = plan->inst[k];
+    if (I.fp32) {  // precision form, pole sum fused into its last kernel
+      HX_TRY(enqueue_refine(plan, I, states[k], s, prof));
+      continue;
+    }
     if (batched(plan, I)) {  // pole sum fused into the leaf downward kernel
       HX_TRY(enqueue_batched(plan, I, states[k], s, prof));
       continue;

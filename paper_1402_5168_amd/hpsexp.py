@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhpsexp.s
 HX_OK, HX_EINVAL, HX_ENOMEM, HX_ESINGULAR = 0, -1, -2, -3
 HX_EUNSTABLE, HX_EDEVICE, HX_ESTATE, HX_ESTAGE = -4, -5, -6, -7
 HX_WAVE_DIRICHLET = 0
-HX_FP64 = 0
+HX_FP64, HX_FP32_REFINE = 0, 1
 HX_FLAG_ALLOW_UNSTABLE, HX_FLAG_NO_GRAPH, HX_FLAG_CHECK_STATE, HX_FLAG_UNBATCHED = 0x1, 0x2, 0x4, 0x8
 
 
@@ -47,9 +47,10 @@ class hx_info(ctypes.Structure):
                 ("max_abs_R", c_double), ("fit_X", c_double), ("sum_abs_b", c_double)]
 
 
-HX_K_LEAF_UP, HX_K_MERGE_UP, HX_K_MERGE_DOWN, HX_K_LEAF_DOWN, HX_K_POLE_SUM = range(5)
-HX_K_CLASSES = 5
-KERNEL_NAMES = ("k_leaf_up", "k_merge_up", "k_merge_down", "k_leaf_down", "k_pole_sum")
+HX_K_LEAF_UP, HX_K_MERGE_UP, HX_K_MERGE_DOWN, HX_K_LEAF_DOWN, HX_K_POLE_SUM, HX_K_RESIDUAL = range(6)
+HX_K_CLASSES = 6
+KERNEL_NAMES = ("k_leaf_up", "k_merge_up", "k_merge_down", "k_leaf_down", "k_pole_sum",
+                "k_residual")
 
 EXPORTS = ("hx_plan_create", "hx_plan_add", "hx_plan_query", "hx_plan_bind",
            "hx_plan_build", "hx_step", "hx_step_profile", "hx_status_str",
@@ -166,9 +167,10 @@ def _cplx_pairs(z) -> np.ndarray:
 class Plan:
     """A plan whose device memory is owned by torch tensors."""
 
-    def __init__(self, device: int = 0, flags: int = 0):
+    def __init__(self, device: int = 0, flags: int = 0, precision: int = HX_FP64):
         self.device = device
-        self.handle = hx_plan_create(HX_FP64, device, flags)
+        self.precision = precision
+        self.handle = hx_plan_create(precision, device, flags)
         self._keep = []          # host arrays referenced by the C structs
         self.arena = None
         self.instances = []

@@ -53,6 +53,7 @@ def status_of(fn):
 
 def test_create_rejects_bad_arguments():
     assert status_of(lambda: hx.hx_plan_create(7, 0, 0)) == hx.HX_EINVAL
+    hx.hx_plan_destroy(hx.hx_plan_create(hx.HX_FP32_REFINE, 0, 0))
     assert status_of(lambda: hx.hx_plan_create(hx.HX_FP64, -1, 0)) == hx.HX_EINVAL
     assert status_of(lambda: hx.hx_plan_create(hx.HX_FP64, 0, 0x100)) == hx.HX_EINVAL
 
@@ -106,8 +107,20 @@ def test_query_reports_sizes_and_fit():
     assert info["max_abs_R"] <= 1 + 1e-6
     assert info["operator_bytes"] > 0 and info["arena_bytes"] > info["operator_bytes"]
     assert info["workspace_min_bytes"] <= info["workspace_bytes"]
-    # op bytes per step: every stored entry once per pole and RHS
+    # 3 right-hand sides are batched: every stored entry is read once per step
+    assert info["op_bytes_per_step"] == pytest.approx(info["operator_bytes"], rel=0.01)
+    plan.close()
+    plan = hx.Plan(flags=hx.HX_FLAG_UNBATCHED)
+    _add(plan, nex=4, ney=2, p=8, nrhs=3)
+    info = plan.query()
     assert info["op_bytes_per_step"] == pytest.approx(3 * info["operator_bytes"], rel=0.01)
+    plan.close()
+    plan = hx.Plan(precision=hx.HX_FP32_REFINE)
+    _add(plan, nex=4, ney=2, p=8, nrhs=3)
+    info32 = plan.query()
+    assert info32["operator_bytes"] * 2 == info["operator_bytes"]
+    # two FP32 sweeps per step read as many bytes as one FP64 sweep
+    assert info32["op_bytes_per_step"] == pytest.approx(info["op_bytes_per_step"] / 3, rel=0.01)
     plan.close()
 
 

@@ -39,10 +39,10 @@ def oracle_run(w, n_steps):
     return [st.run(w.u0[r], w.v0[r], n_steps) for r in range(w.u0.shape[0])]
 
 
-def gpu_run(ws, n_steps, flags=0, split=None, workspace=None):
+def gpu_run(ws, n_steps, flags=0, split=None, workspace=None, precision=0):
     torch = _torch()
     from paper_1402_5168_amd import hpsexp
-    plan = hpsexp.Plan(device=0, flags=flags)
+    plan = hpsexp.Plan(device=0, flags=flags, precision=precision)
     for w in ws:
         m = w.mesh
         plan.add(m.nex, m.ney, m.p, w.c2, w.tau, 1e-10, w.fit.alpha, w.fit.b,
@@ -62,9 +62,12 @@ def gpu_run(ws, n_steps, flags=0, split=None, workspace=None):
 
 def check(w, got, n_steps, tol=TOL):
     ref = oracle_run(w, n_steps)
+    worst = 0.0
     for r, (u, v) in enumerate(ref):
         eu, ev = rel_err(got[r, 0], u), rel_err(got[r, 1], v)
+        worst = max(worst, eu, ev)
         assert eu <= tol and ev <= tol, (r, eu, ev)
+    say(f"max rel err {worst:.3e} (tol {tol:.0e})")
     return ref
 
 
@@ -205,3 +208,27 @@ def test_batched_equals_unbatched():
     a = gpu_run([w], 3)[0]
     b = gpu_run([w], 3, flags=hpsexp.HX_FLAG_UNBATCHED)[0]
     assert rel_err(a, b) <= 1e-13
+
+
+# ---- precision form: FP32 operators and sweeps + FP64 residual correction --------
+
+TOL32 = 1e-7
+
+
+@pytest.mark.parametrize("nex,ney,p,nrhs,steps", [(4, 4, 12, 1, 10), (4, 2, 8, 3, 10),
+                                                  (2, 2, 10, 32, 5), (1, 1, 8, 2, 5),
+                                                  (8, 4, 6, 17, 5), (2, 1, 18, 1, 3)])
+def test_precision_form_matches_oracle(nex, ney, p, nrhs, steps):
+    say(f"fp32+refine {nex}x{ney} p={p} nrhs={nrhs} steps={steps}")
+    w = make(nex, ney, p, n_rhs=nrhs)
+    rng = np.random.default_rng(3 + nrhs)
+    w.v0 = 0.2 * rng.standard_normal(w.u0.shape) * w.u0
+    got = gpu_run([w], steps, precision=1)[0]
+    check(w, got, steps, tol=TOL32)
+
+
+def test_precision_form_wave_4x4_p12_100_steps():
+    say("fp32+refine wave_4x4_p12, 100 steps")
+    w = configs.make(configs.scaled("wave_4x4_p12", 4, 4, n_steps=100))
+    got = gpu_run([w], 100, precision=1)[0]
+    check(w, got, 100, tol=TOL32)
