@@ -4,17 +4,22 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
 One step applies exp(tau L) ~ sum_m b_m (tau L - alpha_m)^{-1} to the state
-(all folded poles, both sweeps of the hierarchical solver, the FP64 pole
-sum).  The timed region is K steps replayed from the library's hipGraph,
-with the state and every operator already resident in HBM; the build
-stage is timed separately.  Prints one JSON line.
+(all folded poles, the sweeps of the hierarchical solver, the FP64 pole
+sum).  The default run is the precision form (FP32 operators and sweeps on
+the matrix cores, one FP64 residual correction per step) with 32 batched
+right-hand sides on 64x64 elements x 10^2 nodes and 131 poles; the same
+inputs are then run in FP64 (batched, and with one right-hand side) for
+the comparison and the accuracy of the precision form.  The timed region
+is K steps replayed from the library's hipGraph, with the state and every
+operator already resident in HBM; the build stage is timed separately.
+Prints one JSON line.
 
 Roofline: the same K steps are run again through hx_step_profile, which
 brackets every kernel with HIP events on its launch stream; the dominant
-kernel's algorithmic bytes per launch divided by its mean duration is
-compared with the 8 TB/s HBM peak.  cpu_baseline: the FP64 CPU oracle
-(sparse LU of the assembled collocation system) timed on a bounded sample
-of the same workload.
+kernel's algorithmic flops (batched) or bytes (one right-hand side) per
+launch divided by its mean duration is compared with the MI355X peak.
+cpu_baseline: the FP64 CPU oracle (sparse LU of the assembled collocation
+system) timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -65,17 +70,18 @@ def algorithmic_bytes(mesh, npole: int, nrhs: int) -> dict:
     return {"k_leaf_up": leaf_up, "k_leaf_down": leaf_down, "k_pole_sum": pole_sum}
 
 
-def cpu_baseline(recipe, npole_folded: int, sub: int = 8, poles: int = 4, reps: int = 5):
+def cpu_baseline(recipe, npole_folded: int, sub: int = 8, poles: int = 4,
+                 min_seconds: float = 10.0):
     """The oracle's step rate on a sub-mesh of the same workload: `poles` of
-    the folded shifts factored (excluded), `reps` resolvent applications each,
-    scaled to all folded poles."""
+    the folded shifts factored (factorisation excluded), their resolvent
+    solves repeated for at least `min_seconds`, scaled to all folded poles."""
     import numpy as np
 
     from oracle import collocation as col
     from workloads import configs
 
     rec = configs.scaled(recipe, sub, sub)
-    w = configs.make(rec)
+    w = configs.make(rec, n_rhs=1)
     m = w.mesh
     grid = col.make_grid(m.nex, m.ney, m.p)
     K, P = col.assemble(grid, w.c2)
@@ -84,55 +90,42 @@ def cpu_baseline(recipe, npole_folded: int, sub: int = 8, poles: int = 4, reps: 
     solvers = [col.ShiftedSolver(K, P, (w.fit.alpha[M + k] / w.tau) ** 2, grid.n_int)
                for k in picks]
     u0, v0 = w.u0[0], w.v0[0]
+    reps = 0
     t0 = time.perf_counter()
-    for _ in range(reps):
+    while True:
         for k, s in zip(picks, solvers):
             a = w.fit.alpha[M + k]
             y = s.solve_interior((a * u0 + w.tau * v0) / w.tau ** 2)
             _ = (a * y + u0) / w.tau
+        reps += 1
+        if time.perf_counter() - t0 >= min_seconds or reps >= 100000:
+            break
     dt = (time.perf_counter() - t0) / (reps * poles)
     step_s = dt * npole_folded
     dof = 2 * m.n_el * m.q * m.q
     return {"value": dof / step_s, "unit": "DOF·steps/s", "cores": 1, "kind": "oracle",
             "sample": (f"{sub}x{sub}-element sub-mesh of the same field and p, "
                        f"{poles} of {npole_folded} folded poles (sparse LU factorisation "
-                       f"excluded), {reps} resolvent solves each, scaled to "
-                       f"{npole_folded} poles; SuperLU solve is single-threaded"),
+                       f"excluded), {reps} resolvent solves each ({dt * 1e3:.2f} ms per "
+                       f"solve), scaled to {npole_folded} poles and one right-hand side; "
+                       f"the SuperLU solve is single-threaded"),
             "step_seconds_sample": step_s}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="wave_32x32_p16")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--nrhs", type=int, default=None,
-                    help="right-hand sides (default: the workload's own count)")
-    ap.add_argument("--unbatched", action="store_true",
-                    help="one pass per right-hand side (reference for the batching speedup)")
-    ap.add_argument("--precision", choices=["fp64", "fp32-refine"], default="fp64")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              "(pole-sharded multi-GPU stepping is not part of this build)", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
+def run(w, precision: str, unbatched: bool, steps: int, warmup: int, profile: bool = True):
+    """Build one plan for the inputs w, time `steps` graph-replayed steps
+    after `warmup` untimed ones, optionally profile the kernels.  Returns the
+    measurements and the final state (host)."""
     import torch
 
     from paper_1402_5168_amd import hpsexp
     from workloads import configs
 
-    rec = configs.RECIPES[args.workload]
-    w = configs.make(rec, n_rhs=args.nrhs)
     m = w.mesh
     nrhs = w.u0.shape[0]
-    flags = hpsexp.HX_FLAG_UNBATCHED if args.unbatched else 0
-    fp32 = args.precision == "fp32-refine"
-    batched = fp32 or (nrhs > 1 and not args.unbatched)
-    plan = hpsexp.Plan(device=0, flags=flags,
+    fp32 = precision == "fp32-refine"
+    batched = fp32 or (nrhs > 1 and not unbatched)
+    plan = hpsexp.Plan(device=0, flags=hpsexp.HX_FLAG_UNBATCHED if unbatched else 0,
                        precision=hpsexp.HX_FP32_REFINE if fp32 else hpsexp.HX_FP64)
     plan.add(m.nex, m.ney, m.p, w.c2, w.tau, configs.DELTA, w.fit.alpha, w.fit.b, nrhs=nrhs)
     info = plan.query()
@@ -142,73 +135,134 @@ def main():
     plan.build()
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
-
     stream = torch.cuda.Stream(device=0)
     state = torch.tensor(w.state(), device="cuda:0")
+    kms = nl = None
     with torch.cuda.stream(stream):
-        plan.step([state], args.warmup, stream=stream)
+        plan.step([state], warmup, stream=stream)
         stream.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(stream)
-        plan.step([state], args.steps, stream=stream)
+        plan.step([state], steps, stream=stream)
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         if not bool(torch.isfinite(state).all()):
             raise RuntimeError("non-finite state after the timed steps")
-        # roofline pass: same kernels, event pairs around each launch
-        state2 = torch.tensor(w.state(), device="cuda:0")
-        kms, nl = plan.step_profile([state2], args.steps, stream=stream)
+        if profile:
+            # roofline pass: same kernels, event pairs around each launch
+            state2 = torch.tensor(w.state(), device="cuda:0")
+            kms, nl = plan.step_profile([state2], steps, stream=stream)
+            del state2
+    final = state.cpu().numpy()
+    plan.close()
+    del plan, state
+    torch.cuda.empty_cache()
+    ms_step = ms / max(steps, 1)
+    out = {"value": info["dof_state"] * steps / (ms / 1e3), "ms_per_step": ms_step,
+           "build_s": build_s, "batched": batched, "info": info}
+    if profile:
+        kernels = {}
+        ab = algorithmic_bytes(m, info["folded_poles"], nrhs)
+        for k, name in enumerate(hpsexp.KERNEL_NAMES):
+            if nl[k] == 0:
+                continue
+            avg = kms[k] / nl[k]
+            entry = {"launches": nl[k], "ms_total": kms[k], "ms_avg": avg}
+            if name in ab and not batched:
+                entry["bytes_per_launch"] = ab[name]
+                entry["GBps"] = ab[name] / (avg * 1e-3) / 1e9
+            kernels[name] = entry
+        dom = kernels["k_leaf_up"]
+        if batched:
+            # each stored entry serves nrhs columns: the sweeps are MFMA-bound
+            flops = leaf_up_flops(m, info["folded_poles"], nrhs)
+            tf = flops / (dom["ms_avg"] * 1e-3) / 1e12
+            dom["flops_per_launch"] = flops
+            dom["TFLOPs"] = tf
+            peak = FP32_PEAK_TFLOPS if fp32 else FP64_PEAK_TFLOPS
+            out["roofline"] = {"bound": "mfma", "kernel": "k_leaf_up", "achieved": tf,
+                               "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
+                               "traffic": None,
+                               "step_TFLOPs": info["flops_per_step"] / (ms_step * 1e-3) / 1e12}
+        else:
+            out["roofline"] = {"bound": "hbm", "kernel": "k_leaf_up", "achieved": dom["GBps"],
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": None,
+                               "step_op_bytes_GBps":
+                                   info["op_bytes_per_step"] / (ms_step * 1e-3) / 1e9}
+        out["kernels"] = kernels
+    return out, final
 
-    ms_step = ms / max(args.steps, 1)
-    value = info["dof_state"] * args.steps / (ms / 1e3)
-    ab = algorithmic_bytes(m, info["folded_poles"], nrhs)
-    kernels = {}
-    for k, name in enumerate(hpsexp.KERNEL_NAMES):
-        if nl[k] == 0:
-            continue
-        avg = kms[k] / nl[k]
-        entry = {"launches": nl[k], "ms_total": kms[k], "ms_avg": avg}
-        if name in ab:
-            entry["bytes_per_launch"] = ab[name]
-            entry["GBps"] = ab[name] / (avg * 1e-3) / 1e9
-        kernels[name] = entry
-    dom = kernels["k_leaf_up"]
-    if batched:
-        # each stored entry is used nrhs times: the sweeps are MFMA-bound
-        tf = leaf_up_flops(m, info["folded_poles"], nrhs) / (dom["ms_avg"] * 1e-3) / 1e12
-        dom["TFLOPs"] = tf
-        peak = FP32_PEAK_TFLOPS if fp32 else FP64_PEAK_TFLOPS
-        roofline = {"bound": "mfma", "kernel": "k_leaf_up", "achieved": tf,
-                    "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
-                    "traffic": None,
-                    "step_TFLOPs": info["flops_per_step"] / (ms_step * 1e-3) / 1e12}
-    else:
-        roofline = {"bound": "hbm", "kernel": "k_leaf_up", "achieved": dom["GBps"],
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["GBps"] / HBM_PEAK_GBS,
-                    "traffic": None,
-                    "step_op_bytes_GBps": info["op_bytes_per_step"] / (ms_step * 1e-3) / 1e9}
 
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="wave_64x64_p10")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the FP64 runs of the same workload")
+    ap.add_argument("--nrhs", type=int, default=None,
+                    help="right-hand sides (default: the workload's own count)")
+    ap.add_argument("--unbatched", action="store_true",
+                    help="one pass per right-hand side (reference for the batching speedup)")
+    ap.add_argument("--precision", choices=["fp64", "fp32-refine"], default="fp32-refine")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(pole-sharded multi-GPU stepping is not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+
+    from workloads import configs
+
+    rec = configs.RECIPES[args.workload]
+    w = configs.make(rec, n_rhs=args.nrhs)
+    m = w.mesh
+    nrhs = w.u0.shape[0]
+    head, final = run(w, args.precision, args.unbatched, args.steps, args.warmup)
+    info = head["info"]
     out = {
-        "metric": METRIC, "value": value, "unit": "DOF·steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "metric": METRIC, "value": head["value"], "unit": "DOF·steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if fp32 else "f64",
+        "dtype": "f32+f64" if args.precision == "fp32-refine" else "f64",
         "data": "synthetic",
         "config": {"workload": rec.name, "elements": f"{m.nex}x{m.ney}", "p": m.p,
                    "poles": rec.npoles, "folded_poles": info["folded_poles"], "nrhs": nrhs,
-                   "precision": args.precision, "batched_rhs": batched, "tau": w.tau, "dof_state": info["dof_state"],
+                   "precision": args.precision, "batched_rhs": head["batched"],
+                   "tau": w.tau, "dof_state": info["dof_state"],
                    "dof_nodes": info["dof_nodes"], "fit_X": info["fit_X"],
                    "max_abs_R": info["max_abs_R"],
                    "operator_GiB": info["operator_bytes"] / 2 ** 30},
-        "dof_nodes_steps_per_s": info["dof_nodes"] * args.steps / (ms / 1e3),
-        "build_s": build_s,
-        "roofline": roofline,
-        "kernels": kernels,
+        "dof_nodes_steps_per_s": info["dof_nodes"] * args.steps * 1e3 /
+                                 (head["ms_per_step"] * args.steps),
+        "build_s": head["build_s"],
+        "roofline": head["roofline"],
+        "kernels": head["kernels"],
     }
-    plan.close()
+    if not args.no_compare and args.precision == "fp32-refine":
+        # the same inputs in FP64: batched, and one right-hand side
+        ref, ref_final = run(w, "fp64", False, args.steps, args.warmup, profile=False)
+        err = 0.0
+        for r in range(nrhs):
+            for f in range(2):
+                x, y = final[r, f], ref_final[r, f]
+                err = max(err, float(np.abs(x - y).max() / np.abs(y).max()))
+        w1 = configs.make(rec, n_rhs=1)
+        one, _ = run(w1, "fp64", False, max(args.steps // 2, 1), 1, profile=False)
+        out["compare"] = {
+            "rel_err_vs_fp64": err,
+            "fp64_batched": {"value": ref["value"], "ms_per_step": ref["ms_per_step"]},
+            "fp64_1rhs": {"value": one["value"], "ms_per_step": one["ms_per_step"]},
+            "speedup_vs_fp64_1rhs": head["value"] / one["value"],
+            "speedup_vs_fp64_batched": head["value"] / ref["value"],
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(rec, info["folded_poles"])
     print(json.dumps(out), flush=True)

@@ -8,8 +8,8 @@
 //   * the element's outward normal derivative at each of its edge slots;
 //     the flux rows' residual at an interface node is minus the sum of its
 //     two elements' values, added by the merge of the correction sweep.
-// One block per (element, pole, group of RR right-hand sides); the grid
-// values and first derivatives live in LDS.
+// One block per (element, group of RR right-hand sides) walks the poles;
+// the state, the grid values and first derivatives live in LDS.
 #include "hx_kernels.h"
 
 namespace hx {
@@ -33,121 +33,154 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a, int RR) {
   extern __shared__ double sm[];
   const int p = a.p, q = a.q, q2 = q * q, pp = p * p;
   const int nrg = (a.nrhs + RR - 1) / RR;
-  int rest = blockIdx.x;
-  const int rg = rest % nrg; rest /= nrg;
-  const int pole = rest % a.npole;
-  const int leaf = rest / a.npole;
+  const int rg = blockIdx.x % nrg;
+  const int leaf = blockIdx.x / nrg;
   const LeafDesc L = a.leaves[leaf];
   const int r = a.nrhs;
+  const int r0 = rg * RR;                             // first right-hand side of the group
   double* Ds = sm;
   double* cs = Ds + pp;
-  double2* U = reinterpret_cast<double2*>(cs + pp);   // [RR][p*p]
-  double2* UX = U + RR * pp;                          // x-derivative on interior rows
-  double2* UY = UX + RR * pp;                         // y-derivative on interior columns
+  // row operators of the element: Mx[jj][i][l] = sx^2 sum_m D[i][m] c2(m,jj) D[m][l]
+  // (interior row jj, interior i, all l) and My[i][jj][l] likewise along columns
+  double* Mx = cs + pp;
+  double* My = Mx + q2 * p;
+  double* st = My + q2 * p;                           // u0, v0: [2][q*q][RR]
+  double2* U = reinterpret_cast<double2*>(st + 2 * RR * q2);   // grid values [p*p][RR]
   for (int t = threadIdx.x; t < pp; t += blockDim.x) {
     Ds[t] = a.D[t];
     cs[t] = a.c2[(long long)L.elem * pp + t];
   }
-  const float2* y0 = a.y0 + ((long long)pole * a.w_pole + (long long)leaf * q2) * r;
-  const float2* ue = a.ue + ((long long)pole * a.e_pole + L.vec_off) * r;
-  for (int idx = threadIdx.x; idx < RR * pp; idx += blockDim.x) {
-    const int jr = idx / pp, node = idx - jr * pp;
-    const int i = node % p, jj = node / p;
-    const int rhs = rg * RR + jr;
-    double2 v = make_double2(0.0, 0.0);
-    if (rhs < r) {
-      const bool ix = (i > 0 && i < p - 1), iy = (jj > 0 && jj < p - 1);
-      if (ix && iy) {
-        const float2 f = y0[(long long)((i - 1) + q * (jj - 1)) * r + rhs];
-        v = make_double2(f.x, f.y);
-      } else if (ix != iy) {  // non-corner edge node
-        const int s = (i == 0) ? 0 : (i == p - 1) ? 1 : (jj == 0) ? 2 : 3;
-        const int t = (s < 2) ? jj - 1 : i - 1;
-        const int sl = slot_of_side(L.side_mask, s);
-        if (sl >= 0) {
-          const float2 f = ue[(long long)(sl * q + t) * r + rhs];
-          v = make_double2(f.x, f.y);
+  for (int idx = threadIdx.x; idx < RR * 2 * q2; idx += blockDim.x) {
+    const int k = idx / RR, jr = idx - k * RR;        // k < 2 q^2: field-major
+    const int rhs = r0 + jr;
+    st[idx] = (rhs < r) ? a.state[rhs * a.rhs_stride + (k >= q2 ? a.n_int - q2 : 0) +
+                                  (long long)L.elem * q2 + k]
+                        : 0.0;
+  }
+  __syncthreads();
+  const double sx2 = a.sx * a.sx, sy2 = a.sy * a.sy;
+  for (int idx = threadIdx.x; idx < q2 * p; idx += blockDim.x) {
+    const int l = idx % p, ij = idx / p;               // ij = (row) * q + (col), interior
+    const int i = ij % q + 1, jj = ij / q + 1;
+    double mx = 0.0, my = 0.0;
+    for (int m = 0; m < p; ++m) {
+      mx += Ds[i * p + m] * cs[m + p * jj] * Ds[m * p + l];
+      my += Ds[jj * p + m] * cs[i + p * m] * Ds[m * p + l];
+    }
+    Mx[((jj - 1) * q + (i - 1)) * p + l] = sx2 * mx;
+    My[((i - 1) * q + (jj - 1)) * p + l] = sy2 * my;
+  }
+  const double itau = 1.0 / a.tau;
+  // grid values of one pole, fetched a pole ahead into registers (at most
+  // kPer per thread) so their HBM latency overlaps the previous pole's work
+  constexpr int kPer = 8;
+  auto fetch = [&](int pole, float2* buf) {
+    const float2* y0 = a.y0 + ((long long)pole * a.w_pole + (long long)leaf * q2) * r + r0;
+    const float2* ue = a.ue + ((long long)pole * a.e_pole + L.vec_off) * r + r0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int idx = threadIdx.x + u * kBlock;
+      float2 v = make_float2(0.f, 0.f);
+      if (idx < RR * pp) {
+        const int node = idx / RR, jr = idx - node * RR;
+        const int i = node % p, jj = node / p;
+        if (r0 + jr < r) {
+          const bool ix = (i > 0 && i < p - 1), iy = (jj > 0 && jj < p - 1);
+          if (ix && iy) {
+            v = y0[(long long)((i - 1) + q * (jj - 1)) * r + jr];
+          } else if (ix != iy) {  // non-corner edge node
+            const int s = (i == 0) ? 0 : (i == p - 1) ? 1 : (jj == 0) ? 2 : 3;
+            const int t = (s < 2) ? jj - 1 : i - 1;
+            const int sl = slot_of_side(L.side_mask, s);
+            if (sl >= 0) v = ue[(long long)(sl * q + t) * r + jr];
+          }
         }
       }
+      buf[u] = v;
     }
-    U[jr * pp + node] = v;
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < RR * pp; idx += blockDim.x) {
-    const int jr = idx / pp, node = idx - jr * pp;
-    const int i = node % p, jj = node / p;
-    const double2* Ur = U + jr * pp;
-    double2 dx = make_double2(0.0, 0.0), dy = dx;
-    if (jj > 0 && jj < p - 1)
-      for (int l = 0; l < p; ++l) {
-        const double d = Ds[i * p + l];
-        dx.x += d * Ur[l + p * jj].x;
-        dx.y += d * Ur[l + p * jj].y;
-      }
-    if (i > 0 && i < p - 1)
-      for (int l = 0; l < p; ++l) {
-        const double d = Ds[jj * p + l];
-        dy.x += d * Ur[i + p * l].x;
-        dy.y += d * Ur[i + p * l].y;
-      }
-    UX[jr * pp + node] = make_double2(a.sx * dx.x, a.sx * dx.y);
-    UY[jr * pp + node] = make_double2(a.sy * dy.x, a.sy * dy.y);
-  }
-  __syncthreads();
-  const double2 al = a.coef[pole].alpha;
-  const double itau = 1.0 / a.tau;
-  // s = (alpha / tau)^2
-  const double sre = (al.x * al.x - al.y * al.y) * itau * itau;
-  const double sim = 2.0 * al.x * al.y * itau * itau;
-  float2* gres = a.gres + ((long long)pole * a.w_pole + (long long)leaf * q2) * r;
-  for (int idx = threadIdx.x; idx < RR * q2; idx += blockDim.x) {
-    const int jr = idx / q2, k = idx - jr * q2;
-    const int rhs = rg * RR + jr;
-    if (rhs >= r) continue;
-    const int i = k % q + 1, jj = k / q + 1;
-    const double2* UXr = UX + jr * pp;
-    const double2* UYr = UY + jr * pp;
-    double2 kx = make_double2(0.0, 0.0), ky = kx;
-    for (int m = 0; m < p; ++m) {
-      const double dxm = Ds[i * p + m] * cs[m + p * jj];
-      kx.x += dxm * UXr[m + p * jj].x;
-      kx.y += dxm * UXr[m + p * jj].y;
-      const double dym = Ds[jj * p + m] * cs[i + p * m];
-      ky.x += dym * UYr[i + p * m].x;
-      ky.y += dym * UYr[i + p * m].y;
+  };
+  float2 nxt[kPer];
+  fetch(0, nxt);
+  for (int pole = 0; pole < a.npole; ++pole) {
+    __syncthreads();   // row operators ready / previous pole done with U
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int idx = threadIdx.x + u * kBlock;
+      if (idx < RR * pp) U[idx] = make_double2(nxt[u].x, nxt[u].y);
     }
-    const double2 y = U[jr * pp + i + p * jj];
-    // (K - s) y
-    const double ar = a.sx * kx.x + a.sy * ky.x - (sre * y.x - sim * y.y);
-    const double ai = a.sx * kx.y + a.sy * ky.y - (sre * y.y + sim * y.x);
-    const double* st = a.state + rhs * a.rhs_stride + (long long)L.elem * q2;
-    const double uu = st[k], vv = st[a.n_int + k];
-    const double gr = fma(al.x * itau * itau, uu, vv * itau);
-    const double gi = al.y * itau * itau * uu;
-    gres[(long long)k * r + rhs] = make_float2((float)(gr - ar), (float)(gi - ai));
-  }
-  double2* dn = a.dn + ((long long)pole * a.e_pole + L.vec_off) * r;
-  for (int idx = threadIdx.x; idx < RR * L.e; idx += blockDim.x) {
-    const int jr = idx / L.e, k = idx - jr * L.e;
-    const int rhs = rg * RR + jr;
-    if (rhs >= r) continue;
-    const int slot = k / q, t = k - slot * q;
-    const int s = side_of_slot_r(L.side_mask, slot);
-    double2 v;
-    if (s == 0) v = UX[jr * pp + 0 + p * (t + 1)], v.x = -v.x, v.y = -v.y;
-    else if (s == 1) v = UX[jr * pp + (p - 1) + p * (t + 1)];
-    else if (s == 2) v = UY[jr * pp + (t + 1) + 0], v.x = -v.x, v.y = -v.y;
-    else v = UY[jr * pp + (t + 1) + p * (p - 1)];
-    dn[(long long)k * r + rhs] = v;
+    __syncthreads();
+    if (pole + 1 < a.npole) fetch(pole + 1, nxt);
+    const double2 al = a.coef[pole].alpha;
+    // s = (alpha / tau)^2
+    const double sre = (al.x * al.x - al.y * al.y) * itau * itau;
+    const double sim = 2.0 * al.x * al.y * itau * itau;
+    float2* gres = a.gres + ((long long)pole * a.w_pole + (long long)leaf * q2) * r + r0;
+    for (int idx = threadIdx.x; idx < RR * q2; idx += blockDim.x) {
+      const int k = idx / RR, jr = idx - k * RR;
+      if (r0 + jr >= r) continue;
+      const int i = k % q + 1, jj = k / q + 1;
+      const double* mx = Mx + ((jj - 1) * q + (i - 1)) * p;
+      const double* my = My + ((i - 1) * q + (jj - 1)) * p;
+      double2 ky = make_double2(0.0, 0.0);
+      for (int l = 0; l < p; ++l) {
+        const double2 ux = U[(l + p * jj) * RR + jr];
+        const double2 uy = U[(i + p * l) * RR + jr];
+        ky.x += mx[l] * ux.x + my[l] * uy.x;
+        ky.y += mx[l] * ux.y + my[l] * uy.y;
+      }
+      const double2 y = U[(i + p * jj) * RR + jr];
+      // (K - s) y
+      const double ar = ky.x - (sre * y.x - sim * y.y);
+      const double ai = ky.y - (sre * y.y + sim * y.x);
+      const double uu = st[k * RR + jr], vv = st[(q2 + k) * RR + jr];
+      const double gr = fma(al.x * itau * itau, uu, vv * itau);
+      const double gi = al.y * itau * itau * uu;
+      gres[(long long)k * r + jr] = make_float2((float)(gr - ar), (float)(gi - ai));
+    }
+    // outward normal derivative at the edge slots: sx D[0 or p-1][.] along the row,
+    // sy D[0 or p-1][.] along the column
+    double2* dn = a.dn + ((long long)pole * a.e_pole + L.vec_off) * r + r0;
+    for (int idx = threadIdx.x; idx < RR * L.e; idx += blockDim.x) {
+      const int k = idx / RR, jr = idx - k * RR;
+      if (r0 + jr >= r) continue;
+      const int slot = k / q, t = k - slot * q;
+      const int s = side_of_slot_r(L.side_mask, slot);
+      const bool xn = s < 2, lo = (s == 0 || s == 2);
+      const double* Dr = Ds + (lo ? 0 : (p - 1)) * p;
+      const double sc = xn ? (lo ? -a.sx : a.sx) : (lo ? -a.sy : a.sy);
+      double2 v = make_double2(0.0, 0.0);
+      for (int l = 0; l < p; ++l) {
+        const double2 u = xn ? U[(l + p * (t + 1)) * RR + jr] : U[((t + 1) + p * l) * RR + jr];
+        v.x += Dr[l] * u.x;
+        v.y += Dr[l] * u.y;
+      }
+      dn[(long long)k * r + jr] = make_double2(sc * v.x, sc * v.y);
+    }
   }
 }
 
+// Bytes of LDS for RR right-hand sides per block.
+static size_t residual_lds(int p, int RR) {
+  const int pp = p * p, q2 = (p - 2) * (p - 2);
+  return sizeof(double) * (2 * (size_t)pp + 2 * (size_t)q2 * p + 2 * (size_t)RR * q2) +
+         sizeof(double2) * (size_t)RR * pp;
+}
+
 hipError_t launch_residual(const ResidualArgs& a, int n_leaf, hipStream_t s) {
-  const int pp = a.p * a.p;
-  const int RR = a.p <= 16 ? 4 : 2;
-  const size_t lds = sizeof(double) * 2 * pp + sizeof(double2) * 3 * (size_t)RR * pp;
+  // right-hand sides per block: up to 32, within 56 KiB of LDS (two to
+  // three blocks per CU), at least 1 (then up to 160 KiB)
+  int RR = 32;
+  while (RR > 1 && (RR / 2 >= a.nrhs || residual_lds(a.p, RR) > 56 * 1024 ||
+                    RR * a.p * a.p > 8 * kBlock))
+    RR /= 2;
+  const size_t lds = residual_lds(a.p, RR);
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_residual),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
   const int nrg = (a.nrhs + RR - 1) / RR;
-  hipLaunchKernelGGL(k_residual, dim3(n_leaf * a.npole * nrg), dim3(kBlock), lds, s, a, RR);
+  hipLaunchKernelGGL(k_residual, dim3(n_leaf * nrg), dim3(kBlock), lds, s, a, RR);
   return hipGetLastError();
 }
 
