@@ -30,7 +30,8 @@
  * device memory of their own during the build.
  *
  * State layout (one instance, nrhs right-hand sides): FP64, real,
- *     state[rhs][field][element][j][i],   field 0 = u, field 1 = v,
+ *     state[rhs][field][element][j][i],   fields (u, v) for the wave
+ *     equation, (v1, v2, eta) for shallow water,
  * element e = ex + nex*ey, interior node (i, j), 1 <= i, j <= p-2, of the
  * element's p x p Chebyshev-Lobatto grid (ascending coordinates, x index
  * fastest).  Only interior nodes carry state; interface values follow from
@@ -63,8 +64,20 @@ typedef enum {
   HX_ESTAGE = -7      /* call out of order (e.g. step before build)       */
 } hx_status;
 
-/* Problem kinds. */
+/* Problem kinds.
+ * HX_WAVE_DIRICHLET: u_t = v, v_t = div(c^2 grad u), u = 0 on the boundary;
+ *   state fields (u, v).
+ * HX_SW_SLIP: linearised rotating shallow water (section 2.1, example 1)
+ *   v_t = -f J v + c grad(eta), eta_t = c div(v), c = sqrt(gH), with slip
+ *   walls n . v = 0; state fields (v1, v2, eta).  Each resolvent solves
+ *   (Lap - s/c^2) eta = (s/(c^2 a)) eta0' + div(v0')/c - (f/(c a)) curl(v0')
+ *   (a = alpha/tau, s = a^2 + f^2, primes: divided by tau) with the oblique
+ *   wall condition a d_n eta - f d_t eta = (a n.v0' - f t.v0')/c, then
+ *   v = (a - f J)(c grad(eta) - v0')/s.  Shallow-water instances run the
+ *   matrix-core sweeps for any nrhs (HX_FLAG_UNBATCHED does not apply)
+ *   and are built with precision HX_FP64 only (else HX_EINVAL). */
 #define HX_WAVE_DIRICHLET 0
+#define HX_SW_SLIP 1
 
 /* Arithmetic of the stored operators and sweeps.
  * HX_FP64: operators, sweeps and pole sum in FP64.
@@ -92,13 +105,16 @@ typedef struct {
   double x0, x1, y0, y1;
 } hx_mesh;
 
-/* Coefficients.  kind = HX_WAVE_DIRICHLET.  c2: host pointer to
+/* Coefficients.  kind = HX_WAVE_DIRICHLET: c2 is a host pointer to
  * nex*ney*p*p doubles, c(x)^2 at every node of every element
- * (element-major, local node i + p*j), finite and > 0.  Copied by
- * hx_plan_add; the caller keeps ownership. */
+ * (element-major, local node i + p*j), finite and > 0, copied by
+ * hx_plan_add (the caller keeps ownership); f and gH are ignored.
+ * kind = HX_SW_SLIP: f (Coriolis frequency, any real) and gH (> 0) are
+ * used, c2 is ignored (may be null). */
 typedef struct {
   int kind;
   const double* c2;
+  double f, gH;
 } hx_coeffs;
 
 /* Rational function R(z) = sum_{m=-M}^{M} b_m / (z - alpha_m) (eq.
@@ -188,7 +204,9 @@ hx_status hx_step(hx_plan* plan, double* const* states, int n_steps, void* strea
 #define HX_K_LEAF_DOWN  3  /* element downward pass: w - S u_e                   */
 #define HX_K_POLE_SUM   4  /* FP64 pole sum and velocity post-map (one RHS)       */
 #define HX_K_RESIDUAL   5  /* FP64 residual of the precision form                 */
-#define HX_K_CLASSES    6
+#define HX_K_SW_PREP    6  /* shallow water: eta, div v, curl v and wall values   */
+#define HX_K_SW_ROOT    7  /* shallow water: root wall system                     */
+#define HX_K_CLASSES    8
 
 /* Diagnostic twin of hx_step: the same kernels, launched eagerly on
  * `stream` with a HIP event pair around every launch.  kernel_ms[c] and

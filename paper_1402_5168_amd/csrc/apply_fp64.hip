@@ -94,12 +94,14 @@ __global__ __launch_bounds__(kBlock) void k_leaf_up(LeafUpArgs a) {
   const int pole = col / a.nrhs, rhs = col - pole * a.nrhs;
   const int q = a.q, q2 = q * q;
   const LeafDesc L = a.leaves[leaf];
-  const double2 al = a.coef[pole].alpha;
-  const double* u0 = a.state + rhs * a.rhs_stride + (long long)L.elem * q2;
-  const double* v0 = u0 + a.n_int;
+  const PoleCoef pc = a.coef[pole];
+  const double* x1 = a.state + rhs * a.rhs_stride + (long long)L.elem * q2;
+  const double* x2 = x1 + a.n_int;
+  const double* x3 = x2 + a.n_int;
   for (int t = threadIdx.x; t < q2; t += blockDim.x) {
-    const double uu = u0[t], vv = v0[t];
-    gs[t] = make_double2(fma(al.x * a.inv_tau2, uu, vv * a.inv_tau), al.y * a.inv_tau2 * uu);
+    const double u1 = x1[t], u2 = x2[t], u3 = a.nsrc > 2 ? x3[t] : 0.0;
+    gs[t] = make_double2(fma(pc.k1.x, u1, fma(pc.k2.x, u2, pc.k3.x * u3)),
+                         fma(pc.k1.y, u1, fma(pc.k2.y, u2, pc.k3.y * u3)));
   }
   __syncthreads();
   const double2* W = a.ops + pole * a.pole_stride + L.op_off;

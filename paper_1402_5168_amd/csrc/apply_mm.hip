@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_up_mm(MmLeafUpArgs<T> a) {
   const int pole = lp % a.npole, leaf = lp / a.npole;
   const int q = a.q, q2 = q * q, q2p = (q2 + 3) & ~3;
   const LeafDesc L = a.leaves[leaf];
-  const double2 al = a.coef[pole].alpha;
+  const PoleCoef pc = a.coef[pole];
   const int r = a.nrhs;
   for (int idx = threadIdx.x; idx < q2p * RT; idx += blockDim.x) {
     const int j = idx / q2p, k = idx - j * q2p;
@@ -173,10 +173,11 @@ __global__ __launch_bounds__(kBlock) void k_leaf_up_mm(MmLeafUpArgs<T> a) {
       if (a.gin) {
         g = a.gin[((long long)pole * a.w_pole + (long long)leaf * q2 + k) * r + rhs];
       } else {
-        const double* u0 = a.state + rhs * a.rhs_stride + (long long)L.elem * q2;
-        const double uu = u0[k], vv = u0[a.n_int + k];
-        g.x = T(fma(al.x * a.inv_tau2, uu, vv * a.inv_tau));
-        g.y = T(al.y * a.inv_tau2 * uu);
+        const double* x1 = a.state + rhs * a.rhs_stride + (long long)L.elem * q2;
+        const double u1 = x1[k], u2 = x1[a.n_int + k];
+        const double u3 = a.nsrc > 2 ? x1[2 * a.n_int + k] : 0.0;
+        g.x = T(fma(pc.k1.x, u1, fma(pc.k2.x, u2, pc.k3.x * u3)));
+        g.y = T(fma(pc.k1.y, u1, fma(pc.k2.y, u2, pc.k3.y * u3)));
       }
     }
     gs[k * BST + j] = g;
@@ -480,6 +481,70 @@ __global__ __launch_bounds__(kBlock) void k_leaf_down_sum_mm(MmLeafDownArgs<T> a
       }
     }
 }
+
+// ---- shallow water: wall values at the root ------------------------------------
+//   eta_b = Q (rhs_b - a h_root),  rhs_b = (a n.v0 - f t.v0) / (c tau)
+// block = (pole, rhs tile, row group of 64 wall slots)
+template <class T, int NT>
+__global__ __launch_bounds__(kBlock) void k_sw_root_mm(SwRootArgs<T> a) {
+  using C = typename MM<T>::C;
+  constexpr int RT = 16 * NT, BST = RT + 1;
+  __shared__ C Bs[kKC * BST];
+  const int n_rt = (a.nrhs + RT - 1) / RT;
+  int rest = blockIdx.x;
+  const int rg = rest % a.row_groups; rest /= a.row_groups;
+  const int rt = rest % n_rt;
+  const int pole = rest / n_rt;
+  const int n = a.n, r = a.nrhs;
+  const double2 al = a.coef[pole].alpha;
+  const double ax = al.x * a.inv_tau, ay = al.y * a.inv_tau;   // a = alpha / tau
+  const double sc = a.inv_tau * a.inv_c;
+  const C* h = a.h + (long long)pole * n * r;
+  const C* Q = a.ops + pole * a.pole_stride + a.q_off;
+  const int row0 = rg * 64 + (threadIdx.x >> 6) * 16;
+  Acc<T, NT> acc;
+  acc.zero();
+  for (int k0 = 0; k0 < n; k0 += kKC) {
+    const int kc = min(kKC, n - k0), kcp = (kc + 3) & ~3;
+    for (int idx = threadIdx.x; idx < kcp * RT; idx += blockDim.x) {
+      const int k = idx / RT, j = idx - k * RT;
+      const int rhs = rt * RT + j;
+      C v;
+      v.x = v.y = T(0);
+      if (k < kc && rhs < r) {
+        const double nv = a.wall[(long long)rhs * 2 * n + k0 + k];
+        const double tv = a.wall[(long long)rhs * 2 * n + n + k0 + k];
+        const C hv = h[(long long)(k0 + k) * r + rhs];
+        v.x = T((ax * nv - a.f * tv) * sc - (ax * double(hv.x) - ay * double(hv.y)));
+        v.y = T(ay * nv * sc - (ax * double(hv.y) + ay * double(hv.x)));
+      }
+      Bs[k * BST + j] = v;
+    }
+    __syncthreads();
+    if (row0 < n) mm_chunk<T, NT>(acc, Q, n, row0, n, k0, kc, Bs, BST);
+    __syncthreads();
+  }
+  if (row0 >= n) return;
+  C* u = a.u + (long long)pole * n * r;
+  mm_emit<T, NT>(acc, row0, n, [&](int row, int j, C c) {
+    const int rhs = rt * RT + j;
+    if (rhs < r) u[(long long)row * r + rhs] = c;
+  });
+}
+
+template <class T>
+hipError_t launch_sw_root_mm(const SwRootArgs<T>& a, hipStream_t s) {
+  const int nt = a.nrhs > 16 ? 2 : 1;
+  const int RT = 16 * nt;
+  const int n_rt = (a.nrhs + RT - 1) / RT;
+  const dim3 grid(a.npole * n_rt * a.row_groups);
+  if (nt == 2) hipLaunchKernelGGL((k_sw_root_mm<T, 2>), grid, dim3(kBlock), 0, s, a);
+  else hipLaunchKernelGGL((k_sw_root_mm<T, 1>), grid, dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_sw_root_mm<double>(const SwRootArgs<double>&, hipStream_t);
+template hipError_t launch_sw_root_mm<float>(const SwRootArgs<float>&, hipStream_t);
 
 // ---- launchers -----------------------------------------------------------------
 

@@ -167,6 +167,22 @@ __global__ __launch_bounds__(kBlock) void k_pack_f32(const double2* __restrict__
   }
 }
 
+// n x n identity (the right-hand side of a batched inversion).
+__global__ __launch_bounds__(kBlock) void k_eye(double2* __restrict__ X, int n) {
+  const long long nn = (long long)n * n;
+  for (long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x; f < nn;
+       f += (long long)gridDim.x * blockDim.x)
+    X[f] = make_double2((f % (n + 1)) == 0 ? 1.0 : 0.0, 0.0);
+}
+
+hipError_t launch_eye(double2* X, int n, hipStream_t s) {
+  long long blocks = ((long long)n * n + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_eye, dim3((unsigned)blocks), dim3(kBlock), 0, s, X, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_pack_f32(const double2* src, float2* dst, long long n, hipStream_t s) {
   long long blocks = (n + kBlock - 1) / kBlock;
   if (blocks > 65536) blocks = 65536;

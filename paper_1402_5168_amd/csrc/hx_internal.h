@@ -53,6 +53,15 @@ struct PoleCoef {
   double2 alpha;  // pole alpha_m
   double2 cu;     // weight of y_m in the new u: b_m (doubled for m > 0)
   double2 cv;     // weight of y_m in tau * new v: b_m alpha_m (doubled for m > 0)
+  // right-hand side of pole m's elliptic solve: g = k1 X1 + k2 X2 + k3 X3
+  // with real source fields X (wave: u0, v0; shallow water: eta0, div, curl)
+  double2 k1, k2, k3;
+};
+
+struct SwCoef {   // shallow-water pole sums (doubled for m > 0)
+  double2 c0;     // b_m            -> eta'
+  double2 c1;     // b_m a_m / s_m  -> E1
+  double2 c2;     // b_m / s_m      -> E2
 };
 
 }  // namespace hx

@@ -14,9 +14,10 @@ struct LeafUpArgs {
   long long pole_stride;
   const LeafDesc* leaves;
   int ncol, nrhs;            // columns = poles * nrhs
-  const double* state;       // [rhs][field][n_int]
-  long long rhs_stride;      // 2 * n_int
+  const double* state;       // source fields X: [rhs][field][n_int]
+  long long rhs_stride;      // fields * n_int
   int n_int;
+  int nsrc;                  // source fields used (2 or 3)
   const PoleCoef* coef;
   double inv_tau, inv_tau2;
   const double* nrow;        // D[0][1..q] then D[p-1][1..q]
@@ -83,9 +84,10 @@ struct MmLeafUpArgs {
   long long pole_stride;
   const LeafDesc* leaves;
   int npole, nrhs, q;
-  const double* state;
+  const double* state;       // source fields X: [rhs][field][n_int]
   long long rhs_stride;
   int n_int;
+  int nsrc;
   const PoleCoef* coef;
   double inv_tau, inv_tau2;
   const double* nrow;
@@ -139,6 +141,71 @@ struct MmLeafDownArgs {
   // y = w - S u_e there, the fused variant sums y0 + w - S u_e (null: unused)
   typename Cplx<T>::type* y0;
 };
+
+// ---- shallow water -----------------------------------------------------------
+
+struct SwPrepArgs {
+  const double* state;       // [rhs][3][n_int]: v1, v2, eta
+  double* prep;              // [rhs][3][n_int]: eta, div v, curl v
+  long long rhs_stride;
+  int n_int, nrhs, q;
+  const double* Dq;          // q x q interior-line differentiation (reference)
+  double sx, sy;
+};
+
+struct SwWallArgs {
+  const double* state;
+  long long rhs_stride;
+  int n_int, nrhs, q, n_wall;
+  const int4* wall;          // per root exterior slot: element, side, node along the side
+  const double* w_lo;        // extrapolation weights to the low / high end of a line
+  const double* w_hi;
+  double* out;               // [rhs][2][n_wall]: n.v, t.v
+};
+
+struct SwRootFormArgs {
+  const double2* T;          // root DtN of each chunk pole
+  long long T_stride;
+  const double* Dt;          // tangential derivative on the wall slots (n x n)
+  int n;
+  double f;
+  const double2* a;          // a = alpha/tau per chunk pole
+  double2* G;                // [chunk][n*n]
+};
+
+template <class T>
+struct SwPostArgs {
+  const LeafDesc* leaves;
+  int npole, nrhs, p, q;
+  const double* D;           // p x p
+  const SwCoef* coef;
+  const typename Cplx<T>::type* y;   // interior solutions [pole][leaf][q*q][rhs]
+  long long y_pole;
+  const typename Cplx<T>::type* ue;  // edge values, level-0 u [pole][sum e][rhs]
+  long long e_pole;
+  double* state;
+  long long rhs_stride;
+  int n_int;
+  double sx, sy, c, f, beta1, beta2, inv_tau;
+};
+
+template <class T>
+struct SwRootArgs {
+  const typename Cplx<T>::type* ops;   // Q of pole k at ops + k*pole_stride + q_off
+  long long pole_stride, q_off;
+  int n, npole, nrhs, row_groups;
+  const PoleCoef* coef;
+  double inv_tau, inv_c, f;
+  const double* wall;                  // [rhs][2][n]: n.v, t.v
+  const typename Cplx<T>::type* h;     // root h [pole][n][rhs]
+  typename Cplx<T>::type* u;           // root u (wall values) [pole][n][rhs]
+};
+
+hipError_t launch_sw_prep(const SwPrepArgs& a, int n_leaf, hipStream_t s);
+hipError_t launch_sw_wall(const SwWallArgs& a, hipStream_t s);
+hipError_t launch_sw_root_form(const SwRootFormArgs& a, int chunk, hipStream_t s);
+template <class T> hipError_t launch_sw_post(const SwPostArgs<T>& a, int n_leaf, hipStream_t s);
+template <class T> hipError_t launch_sw_root_mm(const SwRootArgs<T>& a, hipStream_t s);
 
 // FP64 residual of the collocation equations for the precision form.
 struct ResidualArgs {
@@ -218,5 +285,6 @@ hipError_t launch_leaf_dtn(const LeafDtnArgs& a, hipStream_t s);
 hipError_t launch_merge_gather(const MergeGatherArgs& a, int n_box, hipStream_t s);
 hipError_t launch_nonfinite_check(const double* x, long long n, int* flag, hipStream_t s);
 hipError_t launch_pack_f32(const double2* src, float2* dst, long long n, hipStream_t s);
+hipError_t launch_eye(double2* X, int n, hipStream_t s);
 
 }  // namespace hx

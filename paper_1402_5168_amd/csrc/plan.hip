@@ -24,6 +24,7 @@ using cd = std::complex<double>;
 using hx::BoxDesc;
 using hx::LeafDesc;
 using hx::PoleCoef;
+using hx::SwCoef;
 
 thread_local std::string g_last_error;
 
@@ -107,6 +108,18 @@ struct Instance {
   long long leaf_ops = 0, merge_ops = 0;    // complex elements per pole
   double max_abs_R = 0.0, fit_X = 0.0, sum_abs_b = 0.0;
   bool fp32 = false;                        // precision form: FP32 operators and sweeps
+  // shallow water: wall nodes are exterior unknowns up to the root
+  bool sw = false;
+  int nfield = 2;
+  double f = 0.0, cw = 1.0;                 // Coriolis frequency, sqrt(gH)
+  double beta1 = 0.0, beta2 = 0.0;          // sum_m b a/s, sum_m b/s
+  int n_wall = 0;
+  long long q_off = 0;                      // root wall system Q inside a pole block
+  std::vector<int4> wall;                   // per root exterior slot: element, side, node
+  std::vector<double> Dt;                   // tangential derivative on the wall slots
+  std::vector<double> Dq, w_lo, w_hi;       // interior-line differentiation and end weights
+  std::vector<SwCoef> swcoef;
+  size_t d_prep = 0, d_wallv = 0, d_wall = 0, d_Dq = 0, d_wlo = 0, d_whi = 0, d_swc = 0;
   // arena layout (byte offsets)
   size_t d_ops = 0, d_w = 0, d_leaves = 0, d_idx = 0, d_coef = 0, d_nrow = 0, end = 0;
   size_t d_y0 = 0, d_gres = 0, d_dn = 0, d_c2 = 0, d_D = 0;  // precision form only
@@ -138,7 +151,7 @@ namespace {
 // asks for one pass per right-hand side (the unbatched reference); the
 // precision form always does.
 bool batched(const hx_plan* plan, const Instance& I) {
-  return I.fp32 || (I.nrhs > 1 && !(plan->flags & HX_FLAG_UNBATCHED));
+  return I.fp32 || I.sw || (I.nrhs > 1 && !(plan->flags & HX_FLAG_UNBATCHED));
 }
 
 // ---- rational function checks (eqs. RM_prop1 and RM_prop2) ----------------
@@ -187,7 +200,15 @@ void build_tree(Instance& I) {
   const int n_vert = (nex - 1) * ney * q;
   auto vnode = [&](int vx, int ey, int t) { return (vx + (nex - 1) * ey) * q + t; };
   auto hnode = [&](int ex, int hy, int t) { return n_vert + (ex + nex * hy) * q + t; };
-  const int n_nodes = n_vert + nex * (ney - 1) * q;
+  const int n_iface = n_vert + nex * (ney - 1) * q;
+  // wall nodes (shallow water only): left, right, bottom, top walls
+  auto wnode = [&](int side, int k, int t) {
+    const int off = side == 0 ? 0 : side == 1 ? ney * q : side == 2 ? 2 * ney * q
+                                                                    : 2 * ney * q + nex * q;
+    return n_iface + off + k * q + t;
+  };
+  const int n_nodes = n_iface + (I.sw ? 2 * (nex + ney) * q : 0);
+  std::vector<int4> wall_of(std::max(n_nodes, 1), make_int4(-1, -1, -1, 0));
 
   std::vector<TBox> cur;
   I.leaves.clear();
@@ -201,10 +222,22 @@ void build_tree(Instance& I) {
     for (int ex = 0; ex < nex; ++ex) {
       TBox b{ex, ey, 1, 1, {}};
       int mask = 0;
+      const int el = ex + nex * ey;
+      auto add_wall = [&](int side, int k) {
+        for (int t = 0; t < q; ++t) {
+          const int id = wnode(side, k, t);
+          wall_of[id] = make_int4(el, side, t, 0);
+          b.ext.push_back(id);
+        }
+      };
       if (ex > 0) { mask |= 1; for (int t = 0; t < q; ++t) b.ext.push_back(vnode(ex - 1, ey, t)); }
+      else if (I.sw) { mask |= 1; add_wall(0, ey); }
       if (ex < nex - 1) { mask |= 2; for (int t = 0; t < q; ++t) b.ext.push_back(vnode(ex, ey, t)); }
+      else if (I.sw) { mask |= 2; add_wall(1, ey); }
       if (ey > 0) { mask |= 4; for (int t = 0; t < q; ++t) b.ext.push_back(hnode(ex, ey - 1, t)); }
+      else if (I.sw) { mask |= 4; add_wall(2, ex); }
       if (ey < ney - 1) { mask |= 8; for (int t = 0; t < q; ++t) b.ext.push_back(hnode(ex, ey, t)); }
+      else if (I.sw) { mask |= 8; add_wall(3, ex); }
       for (size_t k = 0; k < b.ext.size(); ++k) {
         int& sl = slot_a[b.ext[k]] < 0 ? slot_a[b.ext[k]] : slot_b[b.ext[k]];
         sl = vec + (int)k;
@@ -305,6 +338,34 @@ void build_tree(Instance& I) {
     nbx = nbx2;
     nby = nby2;
   }
+  // shallow water: the wall slots in the root's exterior order, their
+  // tangential derivative and the root wall system Q (n_wall^2) per pole
+  I.wall.clear();
+  if (I.sw) {
+    const std::vector<int>& rext = cur[0].ext;
+    I.n_wall = (int)rext.size();
+    for (int id : rext) I.wall.push_back(wall_of[id]);
+    const int n = I.n_wall;
+    I.Dt.assign((size_t)n * n, 0.0);
+    std::map<std::pair<int, int>, std::vector<int>> seg;   // (element, side) -> slots by t
+    for (int k = 0; k < n; ++k) {
+      auto& v = seg[{I.wall[k].x, I.wall[k].y}];
+      if ((int)v.size() < q) v.resize(q, -1);
+      v[I.wall[k].z] = k;
+    }
+    const double sx = 2.0 * nex / (I.mesh.x1 - I.mesh.x0), sy = 2.0 * ney / (I.mesh.y1 - I.mesh.y0);
+    for (auto& kv : seg) {
+      const int side = kv.first.second;
+      // t = (-n2, n1): left -d_y, right +d_y, bottom +d_x, top -d_x
+      const double sg = (side == 0 || side == 3) ? -1.0 : 1.0;
+      const double sc = side < 2 ? sy : sx;
+      for (int t1 = 0; t1 < q; ++t1)
+        for (int t2 = 0; t2 < q; ++t2)
+          I.Dt[(size_t)kv.second[t1] + (size_t)kv.second[t2] * n] = sg * sc * I.Dq[t1 * q + t2];
+    }
+    I.q_off = op;
+    op += align_up((size_t)n * n, 8);
+  }
   I.merge_ops = op - I.leaf_ops;
   I.pole_stride = align_up((size_t)op, 16);
 }
@@ -328,6 +389,16 @@ void layout_arena(hx_plan* plan) {
       L.d_g3 = take(cb * (size_t)I.ncol * L.total_n3);
       L.d_boxes = take(sizeof(BoxDesc) * L.boxes.size());
     }
+    if (I.sw) {
+      I.d_prep = take(sizeof(double) * 3 * (size_t)I.nrhs * I.n_leaf * I.q2);
+      I.d_wallv = take(sizeof(double) * 2 * (size_t)I.nrhs * I.n_wall);
+      I.d_wall = take(sizeof(int4) * I.wall.size());
+      I.d_Dq = take(sizeof(double) * I.Dq.size());
+      I.d_wlo = take(sizeof(double) * I.w_lo.size());
+      I.d_whi = take(sizeof(double) * I.w_hi.size());
+      I.d_swc = take(sizeof(SwCoef) * I.swcoef.size());
+      I.d_D = take(sizeof(double) * I.mesh.p * I.mesh.p);
+    }
     if (I.fp32) {
       I.d_y0 = take(cb * (size_t)I.ncol * I.n_leaf * I.q2);
       I.d_gres = take(cb * (size_t)I.ncol * I.n_leaf * I.q2);
@@ -347,7 +418,7 @@ void layout_arena(hx_plan* plan) {
 // Build workspace layout for a chunk of `ch` poles of one instance.
 struct WsLayout {
   size_t A = 0, T0 = 0, T1 = 0, ipiv = 0, info = 0, ptr = 0, c2 = 0, D = 0, sigma = 0,
-         toff = 0, ops64 = 0, total = 0;
+         toff = 0, ops64 = 0, Dt = 0, sa = 0, total = 0;
   long long sizeA = 0, sizeT = 0, sizeIpiv = 0, sizeInfo = 0, sizePtr = 0, n_off = 0;
 };
 
@@ -375,6 +446,11 @@ WsLayout ws_layout(const Instance& I, int ch) {
     w.sizeInfo = std::max(w.sizeInfo, (long long)I.levels[l].boxes.size());
     w.n_off = std::max(w.n_off, (long long)I.levels[l].boxes.size());
   }
+  if (I.sw) {   // root wall system G = a T_root - f D_t, and its pivots
+    w.sizeA = std::max(w.sizeA, (long long)I.n_wall * I.n_wall);
+    w.sizeIpiv = std::max(w.sizeIpiv, (long long)I.n_wall);
+    w.sizeInfo = std::max(w.sizeInfo, 1LL);
+  }
   w.sizePtr = 6 * w.sizeInfo;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -392,6 +468,10 @@ WsLayout ws_layout(const Instance& I, int ch) {
   w.D = take(sizeof(double) * I.mesh.p * I.mesh.p);
   w.sigma = take(sizeof(double2) * ch);
   w.toff = take(sizeof(long long) * 4 * (size_t)std::max<long long>(w.n_off, 1));
+  if (I.sw) {
+    w.Dt = take(sizeof(double) * I.Dt.size());
+    w.sa = take(sizeof(double2) * ch);
+  }
   if (I.fp32) w.ops64 = take(sizeof(double2) * (size_t)I.pole_stride * ch);
   w.total = off;
   return w;
@@ -408,12 +488,18 @@ hx_status validate_add(const hx_mesh* m, const hx_coeffs* c, double tau, double 
   if (!(m->x1 > m->x0) || !(m->y1 > m->y0) || !std::isfinite(m->x0 + m->x1 + m->y0 + m->y1))
     return fail(HX_EINVAL, "empty or non-finite domain");
   if ((long long)m->nex * m->ney > (1LL << 22)) return fail(HX_EINVAL, "mesh too large");
-  if (c->kind != HX_WAVE_DIRICHLET) return fail(HX_EINVAL, "unsupported problem kind %d", c->kind);
-  if (!c->c2) return fail(HX_EINVAL, "c2 is null");
-  const long long n = (long long)m->nex * m->ney * m->p * m->p;
-  for (long long k = 0; k < n; ++k)
-    if (!(std::isfinite(c->c2[k]) && c->c2[k] > 0.0))
-      return fail(HX_EINVAL, "c2[%lld] = %g is not finite and positive", k, c->c2[k]);
+  if (c->kind == HX_WAVE_DIRICHLET) {
+    if (!c->c2) return fail(HX_EINVAL, "c2 is null");
+    const long long n = (long long)m->nex * m->ney * m->p * m->p;
+    for (long long k = 0; k < n; ++k)
+      if (!(std::isfinite(c->c2[k]) && c->c2[k] > 0.0))
+        return fail(HX_EINVAL, "c2[%lld] = %g is not finite and positive", k, c->c2[k]);
+  } else if (c->kind == HX_SW_SLIP) {
+    if (!std::isfinite(c->f)) return fail(HX_EINVAL, "f must be finite");
+    if (!(c->gH > 0.0) || !std::isfinite(c->gH)) return fail(HX_EINVAL, "gH must be finite and > 0");
+  } else {
+    return fail(HX_EINVAL, "unsupported problem kind %d", c->kind);
+  }
   if (!(tau > 0.0) || !std::isfinite(tau)) return fail(HX_EINVAL, "tau must be finite and > 0");
   if (!(delta > 0.0) || !std::isfinite(delta)) return fail(HX_EINVAL, "delta must be finite and > 0");
   if (r->npoles < 1 || r->npoles % 2 == 0 || r->npoles > 4001)
@@ -471,6 +557,44 @@ hx_status check_info(const Build& B, const WsLayout& W, long long n, const char*
   return HX_OK;
 }
 
+// Shallow water: the root's wall values solve (a T_root - f D_t) eta_b =
+// rhs_b - a h_root (the oblique slip condition); Q = (a T_root - f D_t)^{-1}
+// is stored per pole.  Tc holds the root DtN map of every chunk pole.
+hx_status build_root_walls(Build& B, Instance& I, const WsLayout& W, double2* ops, size_t Tc,
+                           int p0, int ch) {
+  const int n = I.n_wall;
+  if (n == 0) return HX_OK;
+  std::vector<double2> av(ch);
+  for (int j = 0; j < ch; ++j) {
+    const cd ap = I.alpha[I.M + p0 + j] / I.tau;
+    av[j] = make_double2(ap.real(), ap.imag());
+  }
+  HX_TRY(upload(B, B.ws + W.sa, av.data(), sizeof(double2) * ch));
+  HX_TRY(upload(B, B.ws + W.Dt, I.Dt.data(), sizeof(double) * I.Dt.size()));
+  hx::SwRootFormArgs rf{};
+  rf.T = wsp<double2>(B, Tc);
+  rf.T_stride = W.sizeT;
+  rf.Dt = wsp<double>(B, W.Dt);
+  rf.n = n;
+  rf.f = I.f;
+  rf.a = wsp<double2>(B, W.sa);
+  rf.G = wsp<double2>(B, W.A);
+  HIP_OK(hx::launch_sw_root_form(rf, ch, B.s));
+  std::vector<void*> ptrs;
+  for (int j = 0; j < ch; ++j) ptrs.push_back(wsp<double2>(B, W.A) + (long long)j * n * n);
+  for (int j = 0; j < ch; ++j) ptrs.push_back(ops + (long long)j * I.pole_stride + I.q_off);
+  HX_TRY(upload(B, B.ws + W.ptr, ptrs.data(), sizeof(void*) * ptrs.size()));
+  for (int j = 0; j < ch; ++j) HIP_OK(hx::launch_eye(ops + (long long)j * I.pole_stride + I.q_off, n, B.s));
+  using P = rocblas_double_complex* const*;
+  void** dptr = wsp<void*>(B, W.ptr);
+  int* ipiv = wsp<int>(B, W.ipiv);
+  int* info = wsp<int>(B, W.info);
+  RB_OK(rocsolver_zgetrf_batched(B.rb, n, n, (P)dptr, n, ipiv, n, info, ch));
+  RB_OK(rocsolver_zgetrs_batched(B.rb, rocblas_operation_none, n, n, (P)dptr, n, ipiv, n,
+                                 (P)(dptr + ch), n, ch));
+  return check_info(B, W, ch, "root wall", (int)I.levels.size() - 1);
+}
+
 hx_status build_chunk(Build& B, Instance& I, const WsLayout& W, int p0, int ch) {
   // FP64 operators of this chunk: straight into the arena, or into the
   // workspace first when the arena holds FP32 operators
@@ -481,7 +605,8 @@ hx_status build_chunk(Build& B, Instance& I, const WsLayout& W, int p0, int ch) 
   const double sy = 2.0 * I.mesh.ney / (I.mesh.y1 - I.mesh.y0);
   std::vector<double2> sig(ch);
   for (int j = 0; j < ch; ++j) {
-    const cd s = std::pow(I.alpha[I.M + p0 + j] / I.tau, 2);
+    const cd ap = I.alpha[I.M + p0 + j] / I.tau;
+    const cd s = I.sw ? (ap * ap + I.f * I.f) / (I.cw * I.cw) : ap * ap;
     sig[j] = make_double2(s.real(), s.imag());
   }
   HX_TRY(upload(B, B.ws + W.sigma, sig.data(), sizeof(double2) * ch));
@@ -646,7 +771,7 @@ hx_status build_chunk(Build& B, Instance& I, const WsLayout& W, int p0, int ch) 
                                   c.n3, &one, (CP)(dptr + c.pV), ext, (CP)(dptr + c.pX), c.n3, &zero,
                                   (P)(dptr + c.pY), ext, c.n));
       // T_par = diag(T11a, T22b) - V X B
-      if (lv + 1 < I.levels.size())
+      if (lv + 1 < I.levels.size() || I.sw)
         RB_OK(rocblas_zgemm_batched(B.rb, rocblas_operation_none, rocblas_operation_none, ext, ext,
                                     c.n3, &mone, (CP)(dptr + c.pV), ext, (CP)(dptr + c.pZ), c.n3, &one,
                                     (P)(dptr + c.pT), ext, c.n));
@@ -655,6 +780,7 @@ hx_status build_chunk(Build& B, Instance& I, const WsLayout& W, int p0, int ch) 
     std::swap(Tc, Tp);
     child_off = poff;
   }
+  if (I.sw) HX_TRY(build_root_walls(B, I, W, ops, Tc, p0, ch));
   if (I.fp32) {
     float2* dst = reinterpret_cast<float2*>(B.plan->arena + I.d_ops) + (long long)p0 * I.pole_stride;
     HIP_OK(hx::launch_pack_f32(ops, dst, (long long)ch * I.pole_stride, B.s));
@@ -721,7 +847,43 @@ hx_status hx_plan_add(hx_plan* plan, const hx_mesh* mesh, const hx_coeffs* coeff
   I.tau = tau;
   I.delta = delta;
   I.fp32 = plan->precision == HX_FP32_REFINE;
-  I.c2.assign(coeffs->c2, coeffs->c2 + (size_t)I.n_leaf * mesh->p * mesh->p);
+  I.sw = coeffs->kind == HX_SW_SLIP;
+  if (I.sw && I.fp32)
+    return fail(HX_EINVAL, "the precision form is implemented for the wave equation only");
+  I.nfield = I.sw ? 3 : 2;
+  if (I.sw) {
+    I.f = coeffs->f;
+    I.cw = std::sqrt(coeffs->gH);
+    I.c2.assign((size_t)I.n_leaf * mesh->p * mesh->p, 1.0);   // Laplacian
+    // interior-line operators on the q interior Chebyshev-Lobatto nodes
+    const int q = I.q, N = mesh->p - 1;
+    std::vector<double> x(q);
+    for (int k = 0; k < q; ++k) x[k] = -std::cos((k + 1) * M_PI / N);
+    std::vector<double> c(q, 1.0);
+    for (int k = 0; k < q; ++k)
+      for (int j = 0; j < q; ++j)
+        if (j != k) c[k] *= x[k] - x[j];
+    I.Dq.assign((size_t)q * q, 0.0);
+    for (int i = 0; i < q; ++i) {
+      double sum = 0.0;
+      for (int j = 0; j < q; ++j)
+        if (j != i) {
+          I.Dq[i * q + j] = (c[i] / c[j]) / (x[i] - x[j]);
+          sum += I.Dq[i * q + j];
+        }
+      I.Dq[i * q + i] = -sum;
+    }
+    I.w_lo.assign(q, 1.0);
+    I.w_hi.assign(q, 1.0);
+    for (int k = 0; k < q; ++k)
+      for (int j = 0; j < q; ++j)
+        if (j != k) {
+          I.w_lo[k] *= (-1.0 - x[j]) / (x[k] - x[j]);
+          I.w_hi[k] *= (1.0 - x[j]) / (x[k] - x[j]);
+        }
+  } else {
+    I.c2.assign(coeffs->c2, coeffs->c2 + (size_t)I.n_leaf * mesh->p * mesh->p);
+  }
   for (int k = 0; k < rational->npoles; ++k) {
     I.alpha.emplace_back(rational->alpha[2 * k], rational->alpha[2 * k + 1]);
     I.b.emplace_back(rational->b[2 * k], rational->b[2 * k + 1]);
@@ -734,15 +896,41 @@ hx_status hx_plan_add(hx_plan* plan, const hx_mesh* mesh, const hx_coeffs* coeff
   cd beta = 0.0;
   for (auto& v : I.b) beta += v;
   I.beta = beta.real();
+  auto d2 = [](cd z) { return make_double2(z.real(), z.imag()); };
   for (int k = 0; k <= I.M; ++k) {
     const cd a = I.alpha[I.M + k], bb = I.b[I.M + k];
     const double f = (k == 0) ? 1.0 : 2.0;
-    const cd cu = f * bb, cv = f * bb * a;
     PoleCoef pc;
-    pc.alpha = make_double2(a.real(), a.imag());
-    pc.cu = make_double2(cu.real(), cu.imag());
-    pc.cv = make_double2(cv.real(), cv.imag());
+    pc.alpha = d2(a);
+    pc.cu = d2(f * bb);
+    pc.cv = d2(f * bb * a);
+    if (!I.sw) {   // g = (alpha u0 + tau v0) / tau^2
+      pc.k1 = d2(a / (I.tau * I.tau));
+      pc.k2 = d2(cd(1.0 / I.tau, 0.0));
+      pc.k3 = d2(cd(0.0, 0.0));
+    } else {       // g = (s/(c^2 a)) eta0/tau + div/(c tau) - (f/(c a)) curl/tau
+      const cd ap = a / I.tau, sp = ap * ap + I.f * I.f;
+      const double c = I.cw;
+      pc.k1 = d2(sp / (c * c * ap * I.tau));
+      pc.k2 = d2(cd(1.0 / (c * I.tau), 0.0));
+      pc.k3 = d2(-I.f / (c * ap * I.tau));
+      SwCoef sc;
+      sc.c0 = d2(f * bb);
+      sc.c1 = d2(f * bb * ap / sp);
+      sc.c2 = d2(f * bb / sp);
+      I.swcoef.push_back(sc);
+    }
     I.coef.push_back(pc);
+  }
+  if (I.sw) {
+    cd b1 = 0.0, b2 = 0.0;
+    for (int k = 0; k < (int)I.alpha.size(); ++k) {
+      const cd ap = I.alpha[k] / I.tau, sp = ap * ap + I.f * I.f;
+      b1 += I.b[k] * ap / sp;
+      b2 += I.b[k] / sp;
+    }
+    I.beta1 = b1.real();
+    I.beta2 = b2.real();
   }
   const std::vector<double> D = cheb_diff(mesh->p);
   for (int k = 1; k <= I.q; ++k) I.nrow.push_back(D[0 * mesh->p + k]);
@@ -768,8 +956,8 @@ hx_status hx_plan_query(const hx_plan* plan, hx_info* info) {
   size_t wmax = 0, wmin = 0;
   for (auto& I : plan->inst) {
     r.operator_bytes += I.cbytes() * (size_t)(I.leaf_ops + I.merge_ops) * I.npole;
-    r.dof_state += 2LL * I.n_leaf * I.q2 * I.nrhs;
-    r.dof_nodes += 2LL * I.n_leaf * I.mesh.p * I.mesh.p * I.nrhs;
+    r.dof_state += (long long)I.nfield * I.n_leaf * I.q2 * I.nrhs;
+    r.dof_nodes += (long long)I.nfield * I.n_leaf * I.mesh.p * I.mesh.p * I.nrhs;
     r.folded_poles += I.npole;
     // every stored entry is read once per column per step
     long long entries = 0;
@@ -818,6 +1006,15 @@ hx_status hx_plan_bind(hx_plan* plan, void* arena, size_t arena_bytes) {
       HIP_OK(hipMemcpy(a + I.d_idx, I.idx.data(), sizeof(int) * I.idx.size(), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(a + I.d_coef, I.coef.data(), sizeof(PoleCoef) * I.coef.size(), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(a + I.d_nrow, I.nrow.data(), sizeof(double) * I.nrow.size(), hipMemcpyHostToDevice));
+    if (I.sw) {
+      const std::vector<double> D = cheb_diff(I.mesh.p);
+      HIP_OK(hipMemcpy(a + I.d_D, D.data(), sizeof(double) * D.size(), hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(a + I.d_wall, I.wall.data(), sizeof(int4) * I.wall.size(), hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(a + I.d_Dq, I.Dq.data(), sizeof(double) * I.Dq.size(), hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(a + I.d_wlo, I.w_lo.data(), sizeof(double) * I.w_lo.size(), hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(a + I.d_whi, I.w_hi.data(), sizeof(double) * I.w_hi.size(), hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(a + I.d_swc, I.swcoef.data(), sizeof(SwCoef) * I.swcoef.size(), hipMemcpyHostToDevice));
+    }
     if (I.fp32) {
       const std::vector<double> D = cheb_diff(I.mesh.p);
       HIP_OK(hipMemcpy(a + I.d_c2, I.c2.data(), sizeof(double) * I.c2.size(), hipMemcpyHostToDevice));
@@ -924,6 +1121,7 @@ hx_status enqueue_batched(hx_plan* plan, const Instance& I, double* state, hipSt
   lu.state = state;
   lu.rhs_stride = 2 * n_int;
   lu.n_int = (int)n_int;
+  lu.nsrc = 2;
   lu.coef = coef;
   lu.inv_tau = 1.0 / I.tau;
   lu.inv_tau2 = 1.0 / (I.tau * I.tau);
@@ -995,6 +1193,167 @@ hx_status enqueue_batched(hx_plan* plan, const Instance& I, double* state, hipSt
   return HX_OK;
 }
 
+// Shallow water: sources (eta, div v, curl v) and wall values of the state,
+// the upward sweep to the root, the root's oblique wall system, the
+// downward sweep, then the pole sums and the velocity recovery.
+hx_status enqueue_sw(hx_plan* plan, const Instance& I, double* state, hipStream_t s, Prof* prof) {
+  char* a = plan->arena;
+  const double2* ops = reinterpret_cast<const double2*>(a + I.d_ops);
+  double2* w = reinterpret_cast<double2*>(a + I.d_w);
+  double* prep = reinterpret_cast<double*>(a + I.d_prep);
+  double* wallv = reinterpret_cast<double*>(a + I.d_wallv);
+  const auto* leaves = reinterpret_cast<const LeafDesc*>(a + I.d_leaves);
+  const auto* coef = reinterpret_cast<const PoleCoef*>(a + I.d_coef);
+  const int* idx = reinterpret_cast<const int*>(a + I.d_idx);
+  const long long n_int = (long long)I.n_leaf * I.q2;
+  auto vec = [&](size_t off) { return reinterpret_cast<double2*>(a + off); };
+  auto dptr = [&](size_t off) { return reinterpret_cast<const double*>(a + off); };
+  const int nt = I.nrhs > 16 ? 2 : 1;
+  const double sx = 2.0 * I.mesh.nex / (I.mesh.x1 - I.mesh.x0);
+  const double sy = 2.0 * I.mesh.ney / (I.mesh.y1 - I.mesh.y0);
+
+  hx::SwPrepArgs pa{};
+  pa.state = state;
+  pa.prep = prep;
+  pa.rhs_stride = 3 * n_int;
+  pa.n_int = (int)n_int;
+  pa.nrhs = I.nrhs;
+  pa.q = I.q;
+  pa.Dq = dptr(I.d_Dq);
+  pa.sx = sx;
+  pa.sy = sy;
+  TIMED(HX_K_SW_PREP, hx::launch_sw_prep(pa, I.n_leaf, s));
+  hx::SwWallArgs wa{};
+  wa.state = state;
+  wa.rhs_stride = 3 * n_int;
+  wa.n_int = (int)n_int;
+  wa.nrhs = I.nrhs;
+  wa.q = I.q;
+  wa.n_wall = I.n_wall;
+  wa.wall = reinterpret_cast<const int4*>(a + I.d_wall);
+  wa.w_lo = dptr(I.d_wlo);
+  wa.w_hi = dptr(I.d_whi);
+  wa.out = wallv;
+  TIMED(HX_K_SW_PREP, hx::launch_sw_wall(wa, s));
+
+  hx::MmLeafUpArgs<double> lu{};
+  lu.ops = ops;
+  lu.pole_stride = I.pole_stride;
+  lu.leaves = leaves;
+  lu.npole = I.npole;
+  lu.nrhs = I.nrhs;
+  lu.q = I.q;
+  lu.state = prep;
+  lu.rhs_stride = 3 * n_int;
+  lu.n_int = (int)n_int;
+  lu.nsrc = 3;
+  lu.coef = coef;
+  lu.inv_tau = 1.0 / I.tau;
+  lu.inv_tau2 = 1.0 / (I.tau * I.tau);
+  lu.nrow = dptr(I.d_nrow);
+  lu.sx = sx;
+  lu.sy = sy;
+  lu.w = w;
+  lu.w_pole = n_int;
+  lu.h = vec(I.levels[0].d_h);
+  lu.h_pole = I.levels[0].total_ext;
+  TIMED(HX_K_LEAF_UP, hx::launch_leaf_up_mm<double>(lu, I.n_leaf, nt, s));
+
+  const size_t nl = I.levels.size();
+  for (size_t l = 1; l < nl; ++l) {
+    const Level& L = I.levels[l];
+    hx::MmMergeArgs<double> m{};
+    m.ops = ops;
+    m.pole_stride = I.pole_stride;
+    m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
+    m.idx = idx;
+    m.npole = I.npole;
+    m.nrhs = I.nrhs;
+    m.row_groups = std::max(1, (L.max_ext + 63) / 64);
+    m.child = vec(I.levels[l - 1].d_h);
+    m.child_pole = I.levels[l - 1].total_ext;
+    m.self = vec(L.d_h);
+    m.self_pole = L.total_ext;
+    m.g3 = vec(L.d_g3);
+    m.g3_pole = L.total_n3;
+    TIMED(HX_K_MERGE_UP, hx::launch_merge_up_mm<double>(m, (int)L.boxes.size(), nt, s));
+  }
+  const Level& R = I.levels[nl - 1];
+  hx::SwRootArgs<double> ra{};
+  ra.ops = ops;
+  ra.pole_stride = I.pole_stride;
+  ra.q_off = I.q_off;
+  ra.n = I.n_wall;
+  ra.npole = I.npole;
+  ra.nrhs = I.nrhs;
+  ra.row_groups = (I.n_wall + 63) / 64;
+  ra.coef = coef;
+  ra.inv_tau = 1.0 / I.tau;
+  ra.inv_c = 1.0 / I.cw;
+  ra.f = I.f;
+  ra.wall = wallv;
+  ra.h = vec(R.d_h);
+  ra.u = vec(R.d_u);
+  TIMED(HX_K_SW_ROOT, hx::launch_sw_root_mm<double>(ra, s));
+  for (size_t l = nl - 1; l >= 1; --l) {
+    const Level& L = I.levels[l];
+    hx::MmMergeArgs<double> m{};
+    m.ops = ops;
+    m.pole_stride = I.pole_stride;
+    m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
+    m.idx = idx;
+    m.npole = I.npole;
+    m.nrhs = I.nrhs;
+    m.row_groups = std::max(1, (L.max_n3 + 63) / 64);
+    m.child = vec(I.levels[l - 1].d_u);
+    m.child_pole = I.levels[l - 1].total_ext;
+    m.self = vec(L.d_u);
+    m.self_pole = L.total_ext;
+    m.g3 = vec(L.d_g3);
+    m.g3_pole = L.total_n3;
+    TIMED(HX_K_MERGE_DOWN, hx::launch_merge_down_mm<double>(m, (int)L.boxes.size(), nt, s));
+  }
+  // element interiors y = w - S u_e, written over w
+  hx::MmLeafDownArgs<double> ld{};
+  ld.ops = ops;
+  ld.pole_stride = I.pole_stride;
+  ld.leaves = leaves;
+  ld.npole = I.npole;
+  ld.nrhs = I.nrhs;
+  ld.q = I.q;
+  ld.row_groups = (I.q2 + 63) / 64;
+  ld.u = vec(I.levels[0].d_u);
+  ld.u_pole = I.levels[0].total_ext;
+  ld.w = w;
+  ld.w_pole = n_int;
+  ld.y0 = w;
+  TIMED(HX_K_LEAF_DOWN, hx::launch_leaf_down_mm<double>(ld, I.n_leaf, nt, s));
+  hx::SwPostArgs<double> po{};
+  po.leaves = leaves;
+  po.npole = I.npole;
+  po.nrhs = I.nrhs;
+  po.p = I.mesh.p;
+  po.q = I.q;
+  po.D = dptr(I.d_D);
+  po.coef = reinterpret_cast<const SwCoef*>(a + I.d_swc);
+  po.y = w;
+  po.y_pole = n_int;
+  po.ue = vec(I.levels[0].d_u);
+  po.e_pole = I.levels[0].total_ext;
+  po.state = state;
+  po.rhs_stride = 3 * n_int;
+  po.n_int = (int)n_int;
+  po.sx = sx;
+  po.sy = sy;
+  po.c = I.cw;
+  po.f = I.f;
+  po.beta1 = I.beta1;
+  po.beta2 = I.beta2;
+  po.inv_tau = 1.0 / I.tau;
+  TIMED(HX_K_POLE_SUM, hx::launch_sw_post<double>(po, I.n_leaf, s));
+  return HX_OK;
+}
+
 // Precision form: FP32 sweep, FP64 residual, FP32 correction sweep, FP64
 // pole sum of the corrected solutions.
 hx_status enqueue_refine(hx_plan* plan, const Instance& I, double* state, hipStream_t s, Prof* prof) {
@@ -1024,6 +1383,7 @@ hx_status enqueue_refine(hx_plan* plan, const Instance& I, double* state, hipStr
     lu.state = state;
     lu.rhs_stride = 2 * n_int;
     lu.n_int = (int)n_int;
+    lu.nsrc = 2;
     lu.coef = coef;
     lu.inv_tau = 1.0 / I.tau;
     lu.inv_tau2 = 1.0 / (I.tau * I.tau);
@@ -1145,6 +1505,7 @@ hx_status enqueue_single(hx_plan* plan, const Instance& I, double* state, hipStr
   lu.state = state;
   lu.rhs_stride = 2 * n_int;
   lu.n_int = (int)n_int;
+  lu.nsrc = 2;
   lu.coef = coef;
   lu.inv_tau = 1.0 / I.tau;
   lu.inv_tau2 = 1.0 / (I.tau * I.tau);
@@ -1214,6 +1575,10 @@ hx_status enqueue_step(hx_plan* plan, double* const* states, hipStream_t s, Prof
   char* a = plan->arena;
   for (size_t k = 0; k < plan->inst.size(); ++k) {
     Instance& I = plan->inst[k];
+    if (I.sw) {  // shallow water, pole sums and velocity recovery in its last kernel
+      HX_TRY(enqueue_sw(plan, I, states[k], s, prof));
+      continue;
+    }
     if (I.fp32) {  // precision form, pole sum fused into its last kernel
       HX_TRY(enqueue_refine(plan, I, states[k], s, prof));
       continue;
@@ -1269,7 +1634,7 @@ hx_status hx_step(hx_plan* plan, double* const* states, int n_steps, void* strea
     HIP_OK(hipMemsetAsync(plan->d_flag, 0, sizeof(int), s));
     for (size_t k = 0; k < plan->inst.size(); ++k) {
       const Instance& I = plan->inst[k];
-      HIP_OK(hx::launch_nonfinite_check(states[k], 2LL * I.n_leaf * I.q2 * I.nrhs, plan->d_flag, s));
+      HIP_OK(hx::launch_nonfinite_check(states[k], (long long)I.nfield * I.n_leaf * I.q2 * I.nrhs, plan->d_flag, s));
     }
     int flag = 0;
     HIP_OK(hipMemcpyAsync(&flag, plan->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));

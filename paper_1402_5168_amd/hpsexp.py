@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhpsexp.s
 
 HX_OK, HX_EINVAL, HX_ENOMEM, HX_ESINGULAR = 0, -1, -2, -3
 HX_EUNSTABLE, HX_EDEVICE, HX_ESTATE, HX_ESTAGE = -4, -5, -6, -7
-HX_WAVE_DIRICHLET = 0
+HX_WAVE_DIRICHLET, HX_SW_SLIP = 0, 1
 HX_FP64, HX_FP32_REFINE = 0, 1
 HX_FLAG_ALLOW_UNSTABLE, HX_FLAG_NO_GRAPH, HX_FLAG_CHECK_STATE, HX_FLAG_UNBATCHED = 0x1, 0x2, 0x4, 0x8
 
@@ -31,7 +31,7 @@ class hx_mesh(ctypes.Structure):
 
 
 class hx_coeffs(ctypes.Structure):
-    _fields_ = [("kind", c_int), ("c2", POINTER(c_double))]
+    _fields_ = [("kind", c_int), ("c2", POINTER(c_double)), ("f", c_double), ("gH", c_double)]
 
 
 class hx_rational(ctypes.Structure):
@@ -47,10 +47,11 @@ class hx_info(ctypes.Structure):
                 ("max_abs_R", c_double), ("fit_X", c_double), ("sum_abs_b", c_double)]
 
 
-HX_K_LEAF_UP, HX_K_MERGE_UP, HX_K_MERGE_DOWN, HX_K_LEAF_DOWN, HX_K_POLE_SUM, HX_K_RESIDUAL = range(6)
-HX_K_CLASSES = 6
+(HX_K_LEAF_UP, HX_K_MERGE_UP, HX_K_MERGE_DOWN, HX_K_LEAF_DOWN, HX_K_POLE_SUM, HX_K_RESIDUAL,
+ HX_K_SW_PREP, HX_K_SW_ROOT) = range(8)
+HX_K_CLASSES = 8
 KERNEL_NAMES = ("k_leaf_up", "k_merge_up", "k_merge_down", "k_leaf_down", "k_pole_sum",
-                "k_residual")
+                "k_residual", "k_sw_prep", "k_sw_root")
 
 EXPORTS = ("hx_plan_create", "hx_plan_add", "hx_plan_query", "hx_plan_bind",
            "hx_plan_build", "hx_step", "hx_step_profile", "hx_status_str",
@@ -180,11 +181,23 @@ class Plan:
         mesh = hx_mesh(nex, ney, p, *[float(v) for v in domain])
         c2 = np.ascontiguousarray(np.asarray(c2, dtype=np.float64).reshape(-1))
         a2, b2 = _cplx_pairs(alpha), _cplx_pairs(b)
-        coeffs = hx_coeffs(HX_WAVE_DIRICHLET, c2.ctypes.data_as(POINTER(c_double)))
+        coeffs = hx_coeffs(HX_WAVE_DIRICHLET, c2.ctypes.data_as(POINTER(c_double)), 0.0, 0.0)
         rat = hx_rational(len(a2) // 2, a2.ctypes.data_as(POINTER(c_double)),
                           b2.ctypes.data_as(POINTER(c_double)))
         k = hx_plan_add(self.handle, mesh, coeffs, tau, delta, rat, nrhs)
-        self.instances.append(dict(nex=nex, ney=ney, p=p, nrhs=nrhs))
+        self.instances.append(dict(nex=nex, ney=ney, p=p, nrhs=nrhs, fields=2))
+        return k
+
+    def add_sw(self, nex: int, ney: int, p: int, f: float, gH: float, tau: float,
+               delta: float, alpha, b, nrhs: int = 1, domain=(0.0, 1.0, 0.0, 1.0)) -> int:
+        """Shallow water with slip walls; state fields (v1, v2, eta)."""
+        mesh = hx_mesh(nex, ney, p, *[float(v) for v in domain])
+        a2, b2 = _cplx_pairs(alpha), _cplx_pairs(b)
+        coeffs = hx_coeffs(HX_SW_SLIP, None, float(f), float(gH))
+        rat = hx_rational(len(a2) // 2, a2.ctypes.data_as(POINTER(c_double)),
+                          b2.ctypes.data_as(POINTER(c_double)))
+        k = hx_plan_add(self.handle, mesh, coeffs, tau, delta, rat, nrhs)
+        self.instances.append(dict(nex=nex, ney=ney, p=p, nrhs=nrhs, fields=3))
         return k
 
     def query(self) -> dict:
@@ -194,7 +207,7 @@ class Plan:
     def state_shape(self, k: int):
         d = self.instances[k]
         q = d["p"] - 2
-        return (d["nrhs"], 2, d["nex"] * d["ney"] * q * q)
+        return (d["nrhs"], d["fields"], d["nex"] * d["ney"] * q * q)
 
     def bind(self):
         import torch

@@ -134,3 +134,23 @@ def test_stage_order_is_enforced():
     assert status_of(lambda: hx.hx_plan_bind(plan.handle, 256 + 8, 1 << 40)) == hx.HX_EINVAL
     assert status_of(lambda: hx.hx_plan_bind(plan.handle, 256, 16)) == hx.HX_ENOMEM
     plan.close()
+
+
+def test_shallow_water_add_validation_and_sizes():
+    fit = calibrated_fit(21)
+    plan = hx.Plan()
+    sw = lambda **k: plan.add_sw(k.get("nex", 4), k.get("ney", 2), k.get("p", 8),
+                                 k.get("f", 1.0), k.get("gH", 1.0), 0.5, 1e-10, fit.alpha,
+                                 fit.b, nrhs=k.get("nrhs", 2))
+    assert status_of(lambda: sw(gH=0.0)) == hx.HX_EINVAL
+    assert status_of(lambda: sw(gH=-1.0)) == hx.HX_EINVAL
+    assert status_of(lambda: sw(f=np.inf)) == hx.HX_EINVAL
+    sw(f=0.0)
+    info = plan.query()
+    q = 6
+    assert info["dof_state"] == 3 * 8 * q * q * 2
+    assert info["dof_nodes"] == 3 * 8 * 64 * 2
+    plan.close()
+    plan = hx.Plan(precision=hx.HX_FP32_REFINE)
+    assert status_of(lambda: sw()) == hx.HX_EINVAL
+    plan.close()

@@ -113,3 +113,80 @@ def scaled(recipe: WaveRecipe | str, nex: int, ney: int, p: int | None = None,
         recipe, name=f"{recipe.name}@{nex}x{ney}",
         mesh=layout.Mesh(nex, ney, p or m.p, m.x0, m.x1, m.y0, m.y1),
         npoles=npoles or recipe.npoles, n_steps=n_steps or recipe.n_steps)
+
+
+# ---- shallow water with slip walls ------------------------------------------------
+
+
+@dataclasses.dataclass(frozen=True)
+class SWRecipe:
+    """Linearised rotating shallow water on the unit square with slip walls.
+
+    Time step (a reading, as for the pulses): the states hold wavenumbers
+    |k| <= kmax (units of pi), whose gravity-inertia frequencies stay below
+    omega_max = sqrt(f^2 + gH (kmax pi)^2); tau = X / omega_max keeps them
+    inside the interval on which the rational function matches e^{ix}."""
+    name: str
+    mesh: layout.Mesh
+    f: float
+    gH: float
+    npoles: int
+    kmax: float
+    seeds: tuple
+    n_steps: int
+
+    @property
+    def nrhs(self) -> int:
+        return len(self.seeds)
+
+
+SW_RECIPES = {
+    # 32 x 32 elements x 12^2 nodes, f = 1, gH = 1, 101 poles, 64 states
+    "sw_32x32_p12": SWRecipe("sw_32x32_p12", layout.Mesh(32, 32, 12), 1.0, 1.0, 101, 30.0,
+                             tuple(range(64)), 100),
+}
+
+
+@dataclasses.dataclass
+class SWInputs:
+    recipe: SWRecipe
+    mesh: layout.Mesh
+    fit: RationalFit
+    tau: float
+    v1: np.ndarray              # (nrhs, n_int)
+    v2: np.ndarray
+    eta: np.ndarray
+
+    def state(self) -> np.ndarray:
+        """[rhs][field][n_int] layout of the C-ABI, fields (v1, v2, eta)."""
+        return np.ascontiguousarray(np.stack([self.v1, self.v2, self.eta], axis=1))
+
+
+def sw_tau(fit: RationalFit, f: float, gH: float, kmax: float) -> float:
+    return fit.X / float(np.sqrt(f * f + gH * (kmax * np.pi) ** 2))
+
+
+def make_sw(recipe: SWRecipe | str, n_rhs: int | None = None) -> SWInputs:
+    if isinstance(recipe, str):
+        recipe = SW_RECIPES[recipe]
+    mesh = recipe.mesh
+    fit = calibrated_fit(recipe.npoles)
+    tau = sw_tau(fit, recipe.f, recipe.gH, recipe.kmax)
+    Xi, Yi = layout.interior_nodes(mesh)
+    seeds = recipe.seeds[:n_rhs] if n_rhs else recipe.seeds
+    fs = [fields.wall_modes_state(Xi, Yi, s, recipe.kmax) for s in seeds]
+    v1, v2, eta = (np.stack([f[k] for f in fs]) for k in range(3))
+    return SWInputs(recipe, mesh, fit, float(tau), v1, v2, eta)
+
+
+def scaled_sw(recipe: SWRecipe | str, nex: int, ney: int, p: int | None = None,
+              npoles: int | None = None, kmax: float | None = None,
+              n_steps: int | None = None) -> SWRecipe:
+    if isinstance(recipe, str):
+        recipe = SW_RECIPES[recipe]
+    m = recipe.mesh
+    return dataclasses.replace(
+        recipe, name=f"{recipe.name}@{nex}x{ney}",
+        mesh=layout.Mesh(nex, ney, p or m.p, m.x0, m.x1, m.y0, m.y1),
+        npoles=npoles or recipe.npoles, kmax=kmax or recipe.kmax,
+        n_steps=n_steps or recipe.n_steps)

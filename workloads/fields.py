@@ -78,3 +78,32 @@ def gaussian_pulse(x, y, seed: int, width=0.05) -> np.ndarray:
 
 def dirichlet_mode(x, y, k: int, l: int) -> np.ndarray:
     return np.sin(k * np.pi * x) * np.sin(l * np.pi * y)
+
+
+def wall_modes_state(x, y, seed: int, kmax: float = 30.0):
+    """Random-phase smooth shallow-water state on [0,1]^2 built from the
+    slip-wall basis (n . v = 0 on every side of the unit square):
+        eta0 = sum a_k  cos(k1 pi x) cos(k2 pi y),
+        v1   = sum a'_k sin(k1 pi x) cos(k2 pi y),
+        v2   = sum a''_k cos(k1 pi x) sin(k2 pi y),
+    over integer k = (k1, k2) >= 0 with 0 < |k| <= kmax, |a| = |k|^-2 (shell
+    energy ~ k^-3) and independent random signs from the seed.  All three
+    fields are divided by max |eta0| over the given points.
+    Returns (v1, v2, eta0), each shaped like x."""
+    rng = np.random.default_rng(seed)
+    kk = np.arange(int(np.floor(kmax)) + 1, dtype=np.float64)
+    K1, K2 = np.meshgrid(kk, kk, indexing="ij")
+    kmod = np.hypot(K1, K2)
+    keep = (kmod > 0) & (kmod <= kmax)
+    amp = np.where(keep, 1.0 / np.where(keep, kmod, 1.0) ** 2, 0.0)
+    a0, a1, a2 = (amp * rng.choice([-1.0, 1.0], size=amp.shape) for _ in range(3))
+    xs, ys = np.asarray(x, dtype=np.float64).reshape(-1), np.asarray(y, dtype=np.float64).reshape(-1)
+    cx, sx_ = np.cos(np.pi * kk[:, None] * xs[None, :]), np.sin(np.pi * kk[:, None] * xs[None, :])
+    cy, sy_ = np.cos(np.pi * kk[:, None] * ys[None, :]), np.sin(np.pi * kk[:, None] * ys[None, :])
+    eta = np.einsum("an,an->n", cx, a0 @ cy)
+    v1 = np.einsum("an,an->n", sx_, a1 @ cy)
+    v2 = np.einsum("an,an->n", cx, a2 @ sy_)
+    scale = 1.0 / np.abs(eta).max()
+    shape = np.shape(x)
+    return ((v1 * scale).reshape(shape), (v2 * scale).reshape(shape),
+            (eta * scale).reshape(shape))
