@@ -74,8 +74,9 @@ typedef enum {
  *   (a = alpha/tau, s = a^2 + f^2, primes: divided by tau) with the oblique
  *   wall condition a d_n eta - f d_t eta = (a n.v0' - f t.v0')/c, then
  *   v = (a - f J)(c grad(eta) - v0')/s.  Shallow-water instances run the
- *   matrix-core sweeps for any nrhs (HX_FLAG_UNBATCHED does not apply)
- *   and are built with precision HX_FP64 only (else HX_EINVAL). */
+ *   matrix-core sweeps for any nrhs (HX_FLAG_UNBATCHED does not apply).
+ *   In the precision form the wall rows join the FP64 residual, and the
+ *   correction sweep's root system takes their residual. */
 #define HX_WAVE_DIRICHLET 0
 #define HX_SW_SLIP 1
 

@@ -512,11 +512,20 @@ __global__ __launch_bounds__(kBlock) void k_sw_root_mm(SwRootArgs<T> a) {
       C v;
       v.x = v.y = T(0);
       if (k < kc && rhs < r) {
-        const double nv = a.wall[(long long)rhs * 2 * n + k0 + k];
-        const double tv = a.wall[(long long)rhs * 2 * n + n + k0 + k];
         const C hv = h[(long long)(k0 + k) * r + rhs];
-        v.x = T((ax * nv - a.f * tv) * sc - (ax * double(hv.x) - ay * double(hv.y)));
-        v.y = T(ay * nv * sc - (ax * double(hv.y) + ay * double(hv.x)));
+        double br, bi;   // wall-row right-hand side
+        if (a.rw) {
+          const double2 w = a.rw[((long long)pole * a.rw_pole + a.wall_info[k0 + k].w) * r + rhs];
+          br = w.x;
+          bi = w.y;
+        } else {
+          const double nv = a.wall[(long long)rhs * 2 * n + k0 + k];
+          const double tv = a.wall[(long long)rhs * 2 * n + n + k0 + k];
+          br = (ax * nv - a.f * tv) * sc;
+          bi = ay * nv * sc;
+        }
+        v.x = T(br - (ax * double(hv.x) - ay * double(hv.y)));
+        v.y = T(bi - (ax * double(hv.y) + ay * double(hv.x)));
       }
       Bs[k * BST + j] = v;
     }

@@ -56,6 +56,7 @@ struct PoleCoef {
   // right-hand side of pole m's elliptic solve: g = k1 X1 + k2 X2 + k3 X3
   // with real source fields X (wave: u0, v0; shallow water: eta0, div, curl)
   double2 k1, k2, k3;
+  double2 sig;    // shift of the elliptic operator: (alpha/tau)^2, or (a^2 + f^2)/c^2
 };
 
 struct SwCoef {   // shallow-water pole sums (doubled for m > 0)

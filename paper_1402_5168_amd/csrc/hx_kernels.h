@@ -187,6 +187,8 @@ struct SwPostArgs {
   long long rhs_stride;
   int n_int;
   double sx, sy, c, f, beta1, beta2, inv_tau;
+  const double* esum;        // precision form: first-sweep sums [rhs][3][leaf][p*p] (null: none)
+  int n_leaf;
 };
 
 template <class T>
@@ -199,6 +201,11 @@ struct SwRootArgs {
   const double* wall;                  // [rhs][2][n]: n.v, t.v
   const typename Cplx<T>::type* h;     // root h [pole][n][rhs]
   typename Cplx<T>::type* u;           // root u (wall values) [pole][n][rhs]
+  // precision form, correction sweep: the wall-row residual at level-0 slot
+  // wall_info[k].w of pole p, rw[(p * rw_pole + slot) * nrhs + rhs] (null: none)
+  const double2* rw;
+  long long rw_pole;
+  const int4* wall_info;
 };
 
 hipError_t launch_sw_prep(const SwPrepArgs& a, int n_leaf, hipStream_t s);
@@ -223,7 +230,18 @@ struct ResidualArgs {
   const float2* ue;          // first-sweep edge values (level-0 u) [pole][sum e][rhs]
   long long e_pole;
   float2* gres;              // residual of the interior rows, same layout as y0
-  double2* dn;               // outward normal derivative at the edge slots, as ue (FP64)
+  double2* dn;               // outward normal derivative at the edge slots, as ue (FP64);
+                             // shallow water: the wall-row residual at wall slots
+  int nsrc;                  // source fields of g (state is the source array)
+  // shallow water only
+  int n_leaf;
+  const int* slot_wall;      // per level-0 slot: wall index, -1 for interface slots
+  const double* wallv;       // [rhs][2][n_wall]: n.v, t.v
+  int n_wall;
+  const double* Dq;          // q x q interior-line differentiation
+  double f, inv_c;
+  const SwCoef* swc;
+  double* esum;              // first-sweep pole sums E0, E1, E2 [rhs][3][leaf][p*p]
 };
 hipError_t launch_residual(const ResidualArgs& a, int n_leaf, hipStream_t s);
 

@@ -119,6 +119,8 @@ struct Instance {
   std::vector<double> Dt;                   // tangential derivative on the wall slots
   std::vector<double> Dq, w_lo, w_hi;       // interior-line differentiation and end weights
   std::vector<SwCoef> swcoef;
+  std::vector<int> slot_wall;               // per level-0 slot: wall index or -1
+  size_t d_esum = 0, d_slotw = 0;           // precision form only
   size_t d_prep = 0, d_wallv = 0, d_wall = 0, d_Dq = 0, d_wlo = 0, d_whi = 0, d_swc = 0;
   // arena layout (byte offsets)
   size_t d_ops = 0, d_w = 0, d_leaves = 0, d_idx = 0, d_coef = 0, d_nrow = 0, end = 0;
@@ -344,7 +346,13 @@ void build_tree(Instance& I) {
   if (I.sw) {
     const std::vector<int>& rext = cur[0].ext;
     I.n_wall = (int)rext.size();
-    for (int id : rext) I.wall.push_back(wall_of[id]);
+    I.slot_wall.assign(std::max(I.levels[0].total_ext, 1), -1);
+    for (int id : rext) {
+      int4 wi = wall_of[id];
+      wi.w = slot_a[id];                     // the wall node's level-0 slot
+      I.slot_wall[wi.w] = (int)I.wall.size();
+      I.wall.push_back(wi);
+    }
     const int n = I.n_wall;
     I.Dt.assign((size_t)n * n, 0.0);
     std::map<std::pair<int, int>, std::vector<int>> seg;   // (element, side) -> slots by t
@@ -397,15 +405,18 @@ void layout_arena(hx_plan* plan) {
       I.d_wlo = take(sizeof(double) * I.w_lo.size());
       I.d_whi = take(sizeof(double) * I.w_hi.size());
       I.d_swc = take(sizeof(SwCoef) * I.swcoef.size());
-      I.d_D = take(sizeof(double) * I.mesh.p * I.mesh.p);
+      if (I.fp32) {
+        I.d_esum = take(sizeof(double) * 3 * (size_t)I.nrhs * I.n_leaf * I.mesh.p * I.mesh.p);
+        I.d_slotw = take(sizeof(int) * I.slot_wall.size());
+      }
     }
     if (I.fp32) {
       I.d_y0 = take(cb * (size_t)I.ncol * I.n_leaf * I.q2);
       I.d_gres = take(cb * (size_t)I.ncol * I.n_leaf * I.q2);
       I.d_dn = take(sizeof(double2) * (size_t)I.ncol * I.levels[0].total_ext);
       I.d_c2 = take(sizeof(double) * I.c2.size());
-      I.d_D = take(sizeof(double) * I.mesh.p * I.mesh.p);
     }
+    if (I.sw || I.fp32) I.d_D = take(sizeof(double) * I.mesh.p * I.mesh.p);
     I.d_leaves = take(sizeof(LeafDesc) * I.leaves.size());
     I.d_idx = take(sizeof(int) * I.idx.size());
     I.d_coef = take(sizeof(PoleCoef) * I.coef.size());
@@ -848,8 +859,6 @@ hx_status hx_plan_add(hx_plan* plan, const hx_mesh* mesh, const hx_coeffs* coeff
   I.delta = delta;
   I.fp32 = plan->precision == HX_FP32_REFINE;
   I.sw = coeffs->kind == HX_SW_SLIP;
-  if (I.sw && I.fp32)
-    return fail(HX_EINVAL, "the precision form is implemented for the wave equation only");
   I.nfield = I.sw ? 3 : 2;
   if (I.sw) {
     I.f = coeffs->f;
@@ -908,12 +917,14 @@ hx_status hx_plan_add(hx_plan* plan, const hx_mesh* mesh, const hx_coeffs* coeff
       pc.k1 = d2(a / (I.tau * I.tau));
       pc.k2 = d2(cd(1.0 / I.tau, 0.0));
       pc.k3 = d2(cd(0.0, 0.0));
+      pc.sig = d2((a / I.tau) * (a / I.tau));
     } else {       // g = (s/(c^2 a)) eta0/tau + div/(c tau) - (f/(c a)) curl/tau
       const cd ap = a / I.tau, sp = ap * ap + I.f * I.f;
       const double c = I.cw;
       pc.k1 = d2(sp / (c * c * ap * I.tau));
       pc.k2 = d2(cd(1.0 / (c * I.tau), 0.0));
       pc.k3 = d2(-I.f / (c * ap * I.tau));
+      pc.sig = d2(sp / (c * c));
       SwCoef sc;
       sc.c0 = d2(f * bb);
       sc.c1 = d2(f * bb * ap / sp);
@@ -967,6 +978,7 @@ hx_status hx_plan_query(const hx_plan* plan, hx_info* info) {
         const long long ext = B.n1 + B.n2;
         entries += (long long)B.n3 * (ext + B.n3) + ext * B.n3;
       }
+    entries += (long long)I.n_wall * I.n_wall;   // shallow water: root wall system
     // one sweep (FP64) or two (precision form) per step; batched right-hand
     // sides share each operator read
     const double sweeps = I.fp32 ? 2.0 : 1.0;
@@ -1006,20 +1018,21 @@ hx_status hx_plan_bind(hx_plan* plan, void* arena, size_t arena_bytes) {
       HIP_OK(hipMemcpy(a + I.d_idx, I.idx.data(), sizeof(int) * I.idx.size(), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(a + I.d_coef, I.coef.data(), sizeof(PoleCoef) * I.coef.size(), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(a + I.d_nrow, I.nrow.data(), sizeof(double) * I.nrow.size(), hipMemcpyHostToDevice));
-    if (I.sw) {
+    if (I.sw || I.fp32) {
       const std::vector<double> D = cheb_diff(I.mesh.p);
       HIP_OK(hipMemcpy(a + I.d_D, D.data(), sizeof(double) * D.size(), hipMemcpyHostToDevice));
+    }
+    if (I.sw && I.fp32)
+      HIP_OK(hipMemcpy(a + I.d_slotw, I.slot_wall.data(), sizeof(int) * I.slot_wall.size(), hipMemcpyHostToDevice));
+    if (I.sw) {
       HIP_OK(hipMemcpy(a + I.d_wall, I.wall.data(), sizeof(int4) * I.wall.size(), hipMemcpyHostToDevice));
       HIP_OK(hipMemcpy(a + I.d_Dq, I.Dq.data(), sizeof(double) * I.Dq.size(), hipMemcpyHostToDevice));
       HIP_OK(hipMemcpy(a + I.d_wlo, I.w_lo.data(), sizeof(double) * I.w_lo.size(), hipMemcpyHostToDevice));
       HIP_OK(hipMemcpy(a + I.d_whi, I.w_hi.data(), sizeof(double) * I.w_hi.size(), hipMemcpyHostToDevice));
       HIP_OK(hipMemcpy(a + I.d_swc, I.swcoef.data(), sizeof(SwCoef) * I.swcoef.size(), hipMemcpyHostToDevice));
     }
-    if (I.fp32) {
-      const std::vector<double> D = cheb_diff(I.mesh.p);
+    if (I.fp32)
       HIP_OK(hipMemcpy(a + I.d_c2, I.c2.data(), sizeof(double) * I.c2.size(), hipMemcpyHostToDevice));
-      HIP_OK(hipMemcpy(a + I.d_D, D.data(), sizeof(double) * D.size(), hipMemcpyHostToDevice));
-    }
     for (auto& L : I.levels)
       if (!L.boxes.empty())
         HIP_OK(hipMemcpy(a + L.d_boxes, L.boxes.data(), sizeof(BoxDesc) * L.boxes.size(), hipMemcpyHostToDevice));
@@ -1195,18 +1208,29 @@ hx_status enqueue_batched(hx_plan* plan, const Instance& I, double* state, hipSt
 
 // Shallow water: sources (eta, div v, curl v) and wall values of the state,
 // the upward sweep to the root, the root's oblique wall system, the
-// downward sweep, then the pole sums and the velocity recovery.
+// downward sweep, then the pole sums and the velocity recovery.  In the
+// precision form (T = float) the sweep runs twice: the FP64 residual of the
+// first (interior rows, flux jumps and wall rows) drives the second, and
+// the first sweep's pole sums, kept in FP64, are added to the second's.
+template <class T>
 hx_status enqueue_sw(hx_plan* plan, const Instance& I, double* state, hipStream_t s, Prof* prof) {
+  using C = typename hx::Cplx<T>::type;
+  constexpr bool refine = sizeof(T) == sizeof(float);
   char* a = plan->arena;
-  const double2* ops = reinterpret_cast<const double2*>(a + I.d_ops);
-  double2* w = reinterpret_cast<double2*>(a + I.d_w);
+  const C* ops = reinterpret_cast<const C*>(a + I.d_ops);
+  C* w = reinterpret_cast<C*>(a + I.d_w);
   double* prep = reinterpret_cast<double*>(a + I.d_prep);
   double* wallv = reinterpret_cast<double*>(a + I.d_wallv);
   const auto* leaves = reinterpret_cast<const LeafDesc*>(a + I.d_leaves);
   const auto* coef = reinterpret_cast<const PoleCoef*>(a + I.d_coef);
+  const auto* swc = reinterpret_cast<const SwCoef*>(a + I.d_swc);
+  const auto* wall = reinterpret_cast<const int4*>(a + I.d_wall);
   const int* idx = reinterpret_cast<const int*>(a + I.d_idx);
+  double2* dn = refine ? reinterpret_cast<double2*>(a + I.d_dn) : nullptr;
+  C* gres = refine ? reinterpret_cast<C*>(a + I.d_gres) : nullptr;
+  double* esum = refine ? reinterpret_cast<double*>(a + I.d_esum) : nullptr;
   const long long n_int = (long long)I.n_leaf * I.q2;
-  auto vec = [&](size_t off) { return reinterpret_cast<double2*>(a + off); };
+  auto vec = [&](size_t off) { return reinterpret_cast<C*>(a + off); };
   auto dptr = [&](size_t off) { return reinterpret_cast<const double*>(a + off); };
   const int nt = I.nrhs > 16 ? 2 : 1;
   const double sx = 2.0 * I.mesh.nex / (I.mesh.x1 - I.mesh.x0);
@@ -1230,112 +1254,156 @@ hx_status enqueue_sw(hx_plan* plan, const Instance& I, double* state, hipStream_
   wa.nrhs = I.nrhs;
   wa.q = I.q;
   wa.n_wall = I.n_wall;
-  wa.wall = reinterpret_cast<const int4*>(a + I.d_wall);
+  wa.wall = wall;
   wa.w_lo = dptr(I.d_wlo);
   wa.w_hi = dptr(I.d_whi);
   wa.out = wallv;
   TIMED(HX_K_SW_PREP, hx::launch_sw_wall(wa, s));
 
-  hx::MmLeafUpArgs<double> lu{};
-  lu.ops = ops;
-  lu.pole_stride = I.pole_stride;
-  lu.leaves = leaves;
-  lu.npole = I.npole;
-  lu.nrhs = I.nrhs;
-  lu.q = I.q;
-  lu.state = prep;
-  lu.rhs_stride = 3 * n_int;
-  lu.n_int = (int)n_int;
-  lu.nsrc = 3;
-  lu.coef = coef;
-  lu.inv_tau = 1.0 / I.tau;
-  lu.inv_tau2 = 1.0 / (I.tau * I.tau);
-  lu.nrow = dptr(I.d_nrow);
-  lu.sx = sx;
-  lu.sy = sy;
-  lu.w = w;
-  lu.w_pole = n_int;
-  lu.h = vec(I.levels[0].d_h);
-  lu.h_pole = I.levels[0].total_ext;
-  TIMED(HX_K_LEAF_UP, hx::launch_leaf_up_mm<double>(lu, I.n_leaf, nt, s));
+  const int passes = refine ? 2 : 1;
+  for (int pass = 0; pass < passes; ++pass) {
+    hx::MmLeafUpArgs<T> lu{};
+    lu.ops = ops;
+    lu.pole_stride = I.pole_stride;
+    lu.leaves = leaves;
+    lu.npole = I.npole;
+    lu.nrhs = I.nrhs;
+    lu.q = I.q;
+    lu.state = prep;
+    lu.rhs_stride = 3 * n_int;
+    lu.n_int = (int)n_int;
+    lu.nsrc = 3;
+    lu.coef = coef;
+    lu.inv_tau = 1.0 / I.tau;
+    lu.inv_tau2 = 1.0 / (I.tau * I.tau);
+    lu.nrow = dptr(I.d_nrow);
+    lu.sx = sx;
+    lu.sy = sy;
+    lu.w = w;
+    lu.w_pole = n_int;
+    lu.h = vec(I.levels[0].d_h);
+    lu.h_pole = I.levels[0].total_ext;
+    lu.gin = pass ? gres : nullptr;
+    TIMED(HX_K_LEAF_UP, hx::launch_leaf_up_mm<T>(lu, I.n_leaf, nt, s));
 
-  const size_t nl = I.levels.size();
-  for (size_t l = 1; l < nl; ++l) {
-    const Level& L = I.levels[l];
-    hx::MmMergeArgs<double> m{};
-    m.ops = ops;
-    m.pole_stride = I.pole_stride;
-    m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
-    m.idx = idx;
-    m.npole = I.npole;
-    m.nrhs = I.nrhs;
-    m.row_groups = std::max(1, (L.max_ext + 63) / 64);
-    m.child = vec(I.levels[l - 1].d_h);
-    m.child_pole = I.levels[l - 1].total_ext;
-    m.self = vec(L.d_h);
-    m.self_pole = L.total_ext;
-    m.g3 = vec(L.d_g3);
-    m.g3_pole = L.total_n3;
-    TIMED(HX_K_MERGE_UP, hx::launch_merge_up_mm<double>(m, (int)L.boxes.size(), nt, s));
+    const size_t nl = I.levels.size();
+    for (size_t l = 1; l < nl; ++l) {
+      const Level& L = I.levels[l];
+      hx::MmMergeArgs<T> m{};
+      m.ops = ops;
+      m.pole_stride = I.pole_stride;
+      m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
+      m.idx = idx;
+      m.npole = I.npole;
+      m.nrhs = I.nrhs;
+      m.row_groups = std::max(1, (L.max_ext + 63) / 64);
+      m.child = vec(I.levels[l - 1].d_h);
+      m.child_pole = I.levels[l - 1].total_ext;
+      m.self = vec(L.d_h);
+      m.self_pole = L.total_ext;
+      m.g3 = vec(L.d_g3);
+      m.g3_pole = L.total_n3;
+      m.dn = pass ? dn : nullptr;
+      m.dn_pole = I.levels[0].total_ext;
+      TIMED(HX_K_MERGE_UP, hx::launch_merge_up_mm<T>(m, (int)L.boxes.size(), nt, s));
+    }
+    const Level& R = I.levels[nl - 1];
+    hx::SwRootArgs<T> ra{};
+    ra.ops = ops;
+    ra.pole_stride = I.pole_stride;
+    ra.q_off = I.q_off;
+    ra.n = I.n_wall;
+    ra.npole = I.npole;
+    ra.nrhs = I.nrhs;
+    ra.row_groups = (I.n_wall + 63) / 64;
+    ra.coef = coef;
+    ra.inv_tau = 1.0 / I.tau;
+    ra.inv_c = 1.0 / I.cw;
+    ra.f = I.f;
+    ra.wall = wallv;
+    ra.h = vec(R.d_h);
+    ra.u = vec(R.d_u);
+    ra.rw = pass ? dn : nullptr;
+    ra.rw_pole = I.levels[0].total_ext;
+    ra.wall_info = wall;
+    TIMED(HX_K_SW_ROOT, hx::launch_sw_root_mm<T>(ra, s));
+    for (size_t l = nl - 1; l >= 1; --l) {
+      const Level& L = I.levels[l];
+      hx::MmMergeArgs<T> m{};
+      m.ops = ops;
+      m.pole_stride = I.pole_stride;
+      m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
+      m.idx = idx;
+      m.npole = I.npole;
+      m.nrhs = I.nrhs;
+      m.row_groups = std::max(1, (L.max_n3 + 63) / 64);
+      m.child = vec(I.levels[l - 1].d_u);
+      m.child_pole = I.levels[l - 1].total_ext;
+      m.self = vec(L.d_u);
+      m.self_pole = L.total_ext;
+      m.g3 = vec(L.d_g3);
+      m.g3_pole = L.total_n3;
+      TIMED(HX_K_MERGE_DOWN, hx::launch_merge_down_mm<T>(m, (int)L.boxes.size(), nt, s));
+    }
+    // element interiors y = w - S u_e: over w, or into y0 (first sweep of
+    // the precision form)
+    hx::MmLeafDownArgs<T> ld{};
+    ld.ops = ops;
+    ld.pole_stride = I.pole_stride;
+    ld.leaves = leaves;
+    ld.npole = I.npole;
+    ld.nrhs = I.nrhs;
+    ld.q = I.q;
+    ld.row_groups = (I.q2 + 63) / 64;
+    ld.u = vec(I.levels[0].d_u);
+    ld.u_pole = I.levels[0].total_ext;
+    ld.w = w;
+    ld.w_pole = n_int;
+    ld.y0 = (refine && pass == 0) ? vec(I.d_y0) : w;
+    TIMED(HX_K_LEAF_DOWN, hx::launch_leaf_down_mm<T>(ld, I.n_leaf, nt, s));
+    if (refine && pass == 0) {
+      hx::ResidualArgs rs{};
+      rs.leaves = leaves;
+      rs.npole = I.npole;
+      rs.nrhs = I.nrhs;
+      rs.p = I.mesh.p;
+      rs.q = I.q;
+      rs.c2 = dptr(I.d_c2);
+      rs.D = dptr(I.d_D);
+      rs.sx = sx;
+      rs.sy = sy;
+      rs.tau = I.tau;
+      rs.coef = coef;
+      rs.state = prep;
+      rs.rhs_stride = 3 * n_int;
+      rs.n_int = (int)n_int;
+      rs.y0 = reinterpret_cast<const float2*>(a + I.d_y0);
+      rs.w_pole = n_int;
+      rs.ue = reinterpret_cast<const float2*>(a + I.levels[0].d_u);
+      rs.e_pole = I.levels[0].total_ext;
+      rs.gres = reinterpret_cast<float2*>(gres);
+      rs.dn = dn;
+      rs.nsrc = 3;
+      rs.n_leaf = I.n_leaf;
+      rs.slot_wall = reinterpret_cast<const int*>(a + I.d_slotw);
+      rs.wallv = wallv;
+      rs.n_wall = I.n_wall;
+      rs.Dq = dptr(I.d_Dq);
+      rs.f = I.f;
+      rs.inv_c = 1.0 / I.cw;
+      rs.swc = swc;
+      rs.esum = esum;
+      TIMED(HX_K_RESIDUAL, hx::launch_residual(rs, I.n_leaf, s));
+    }
   }
-  const Level& R = I.levels[nl - 1];
-  hx::SwRootArgs<double> ra{};
-  ra.ops = ops;
-  ra.pole_stride = I.pole_stride;
-  ra.q_off = I.q_off;
-  ra.n = I.n_wall;
-  ra.npole = I.npole;
-  ra.nrhs = I.nrhs;
-  ra.row_groups = (I.n_wall + 63) / 64;
-  ra.coef = coef;
-  ra.inv_tau = 1.0 / I.tau;
-  ra.inv_c = 1.0 / I.cw;
-  ra.f = I.f;
-  ra.wall = wallv;
-  ra.h = vec(R.d_h);
-  ra.u = vec(R.d_u);
-  TIMED(HX_K_SW_ROOT, hx::launch_sw_root_mm<double>(ra, s));
-  for (size_t l = nl - 1; l >= 1; --l) {
-    const Level& L = I.levels[l];
-    hx::MmMergeArgs<double> m{};
-    m.ops = ops;
-    m.pole_stride = I.pole_stride;
-    m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
-    m.idx = idx;
-    m.npole = I.npole;
-    m.nrhs = I.nrhs;
-    m.row_groups = std::max(1, (L.max_n3 + 63) / 64);
-    m.child = vec(I.levels[l - 1].d_u);
-    m.child_pole = I.levels[l - 1].total_ext;
-    m.self = vec(L.d_u);
-    m.self_pole = L.total_ext;
-    m.g3 = vec(L.d_g3);
-    m.g3_pole = L.total_n3;
-    TIMED(HX_K_MERGE_DOWN, hx::launch_merge_down_mm<double>(m, (int)L.boxes.size(), nt, s));
-  }
-  // element interiors y = w - S u_e, written over w
-  hx::MmLeafDownArgs<double> ld{};
-  ld.ops = ops;
-  ld.pole_stride = I.pole_stride;
-  ld.leaves = leaves;
-  ld.npole = I.npole;
-  ld.nrhs = I.nrhs;
-  ld.q = I.q;
-  ld.row_groups = (I.q2 + 63) / 64;
-  ld.u = vec(I.levels[0].d_u);
-  ld.u_pole = I.levels[0].total_ext;
-  ld.w = w;
-  ld.w_pole = n_int;
-  ld.y0 = w;
-  TIMED(HX_K_LEAF_DOWN, hx::launch_leaf_down_mm<double>(ld, I.n_leaf, nt, s));
-  hx::SwPostArgs<double> po{};
+  hx::SwPostArgs<T> po{};
   po.leaves = leaves;
   po.npole = I.npole;
   po.nrhs = I.nrhs;
   po.p = I.mesh.p;
   po.q = I.q;
   po.D = dptr(I.d_D);
-  po.coef = reinterpret_cast<const SwCoef*>(a + I.d_swc);
+  po.coef = swc;
   po.y = w;
   po.y_pole = n_int;
   po.ue = vec(I.levels[0].d_u);
@@ -1350,7 +1418,9 @@ hx_status enqueue_sw(hx_plan* plan, const Instance& I, double* state, hipStream_
   po.beta1 = I.beta1;
   po.beta2 = I.beta2;
   po.inv_tau = 1.0 / I.tau;
-  TIMED(HX_K_POLE_SUM, hx::launch_sw_post<double>(po, I.n_leaf, s));
+  po.esum = esum;
+  po.n_leaf = I.n_leaf;
+  TIMED(HX_K_POLE_SUM, hx::launch_sw_post<T>(po, I.n_leaf, s));
   return HX_OK;
 }
 
@@ -1478,6 +1548,7 @@ hx_status enqueue_refine(hx_plan* plan, const Instance& I, double* state, hipStr
       ra.e_pole = I.levels[0].total_ext;
       ra.gres = gres;
       ra.dn = dn;
+      ra.nsrc = 2;
       TIMED(HX_K_RESIDUAL, hx::launch_residual(ra, I.n_leaf, s));
     } else {
       TIMED(HX_K_LEAF_DOWN, hx::launch_leaf_down_sum_mm<float>(ld, I.n_leaf, nt, s));
@@ -1576,7 +1647,8 @@ hx_status enqueue_step(hx_plan* plan, double* const* states, hipStream_t s, Prof
   for (size_t k = 0; k < plan->inst.size(); ++k) {
     Instance& I = plan->inst[k];
     if (I.sw) {  // shallow water, pole sums and velocity recovery in its last kernel
-      HX_TRY(enqueue_sw(plan, I, states[k], s, prof));
+      if (I.fp32) HX_TRY(enqueue_sw<float>(plan, I, states[k], s, prof));
+      else HX_TRY(enqueue_sw<double>(plan, I, states[k], s, prof));
       continue;
     }
     if (I.fp32) {  // precision form, pole sum fused into its last kernel

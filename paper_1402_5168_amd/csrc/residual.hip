@@ -2,14 +2,20 @@
 //
 // After the FP32 sweep every pole has a solution y0 on the element interiors
 // and values u_e on the element edges.  Assembled on an element's full
-// p x p grid (zero on the outer boundary), they give, in FP64,
+// p x p grid (zero on a Dirichlet boundary), they give, in FP64,
 //   * the residual of the PDE rows at the interior nodes (section 2.2):
-//       res = g - (sx^2 Dx C^2 Dx + sy^2 Dy C^2 Dy - s) y,  g = (alpha u + tau v)/tau^2,
+//       res = g - (sx^2 Dx C^2 Dx + sy^2 Dy C^2 Dy - sigma) y,
+//     g = k1 X1 + k2 X2 (+ k3 X3) from the source fields X of the step;
 //   * the element's outward normal derivative at each of its edge slots;
 //     the flux rows' residual at an interface node is minus the sum of its
-//     two elements' values, added by the merge of the correction sweep.
+//     two elements' values, added by the merge of the correction sweep;
+//   * shallow water: at a wall slot, the residual of the oblique wall row,
+//       rhs_b - (a d_n y - f d_t y),  rhs_b = (a n.v0 - f t.v0)/(tau c),
+//     stored in place of the normal derivative (a wall node has one element),
+//     and the first sweep's pole sums E0, E1, E2 on the element's full grid,
+//     kept in registers across the poles and written once.
 // One block per (element, group of RR right-hand sides) walks the poles;
-// the state, the grid values and first derivatives live in LDS.
+// the sources, the grid values and the row operators live in LDS.
 #include "hx_kernels.h"
 
 namespace hx {
@@ -29,6 +35,7 @@ __device__ __forceinline__ int side_of_slot_r(int mask, int slot) {
   return -1;
 }
 
+template <bool SW>
 __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a, int RR) {
   extern __shared__ double sm[];
   const int p = a.p, q = a.q, q2 = q * q, pp = p * p;
@@ -44,17 +51,19 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a, int RR) {
   // (interior row jj, interior i, all l) and My[i][jj][l] likewise along columns
   double* Mx = cs + pp;
   double* My = Mx + q2 * p;
-  double* st = My + q2 * p;                           // u0, v0: [2][q*q][RR]
-  double2* U = reinterpret_cast<double2*>(st + 2 * RR * q2);   // grid values [p*p][RR]
+  const int ns = a.nsrc;
+  double* st = My + q2 * p;                           // sources: [nsrc][q*q][RR]
+  double2* U = reinterpret_cast<double2*>(st + ns * RR * q2);   // grid values [p*p][RR]
   for (int t = threadIdx.x; t < pp; t += blockDim.x) {
     Ds[t] = a.D[t];
     cs[t] = a.c2[(long long)L.elem * pp + t];
   }
-  for (int idx = threadIdx.x; idx < RR * 2 * q2; idx += blockDim.x) {
-    const int k = idx / RR, jr = idx - k * RR;        // k < 2 q^2: field-major
+  for (int idx = threadIdx.x; idx < RR * ns * q2; idx += blockDim.x) {
+    const int k = idx / RR, jr = idx - k * RR;        // k < nsrc q^2: field-major
+    const int fld = k / q2, kk = k - fld * q2;
     const int rhs = r0 + jr;
-    st[idx] = (rhs < r) ? a.state[rhs * a.rhs_stride + (k >= q2 ? a.n_int - q2 : 0) +
-                                  (long long)L.elem * q2 + k]
+    st[idx] = (rhs < r) ? a.state[rhs * a.rhs_stride + (long long)fld * a.n_int +
+                                  (long long)L.elem * q2 + kk]
                         : 0.0;
   }
   __syncthreads();
@@ -100,20 +109,34 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a, int RR) {
     }
   };
   float2 nxt[kPer];
+  double e0[SW ? kPer : 1], e1[SW ? kPer : 1], e2[SW ? kPer : 1];   // pole sums, SW only
+  if constexpr (SW) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) e0[u] = e1[u] = e2[u] = 0.0;
+  }
   fetch(0, nxt);
   for (int pole = 0; pole < a.npole; ++pole) {
     __syncthreads();   // row operators ready / previous pole done with U
+    SwCoef sc3;
+    if constexpr (SW) sc3 = a.swc[pole];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int idx = threadIdx.x + u * kBlock;
-      if (idx < RR * pp) U[idx] = make_double2(nxt[u].x, nxt[u].y);
+      if (idx < RR * pp) {
+        U[idx] = make_double2(nxt[u].x, nxt[u].y);
+        if constexpr (SW) {
+          const double yr = nxt[u].x, yi = nxt[u].y;
+          e0[u] += sc3.c0.x * yr - sc3.c0.y * yi;
+          e1[u] += sc3.c1.x * yr - sc3.c1.y * yi;
+          e2[u] += sc3.c2.x * yr - sc3.c2.y * yi;
+        }
+      }
     }
     __syncthreads();
     if (pole + 1 < a.npole) fetch(pole + 1, nxt);
-    const double2 al = a.coef[pole].alpha;
-    // s = (alpha / tau)^2
-    const double sre = (al.x * al.x - al.y * al.y) * itau * itau;
-    const double sim = 2.0 * al.x * al.y * itau * itau;
+    const PoleCoef pc = a.coef[pole];
+    const double2 al = pc.alpha;
+    const double sre = pc.sig.x, sim = pc.sig.y;
     float2* gres = a.gres + ((long long)pole * a.w_pole + (long long)leaf * q2) * r + r0;
     for (int idx = threadIdx.x; idx < RR * q2; idx += blockDim.x) {
       const int k = idx / RR, jr = idx - k * RR;
@@ -132,9 +155,10 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a, int RR) {
       // (K - s) y
       const double ar = ky.x - (sre * y.x - sim * y.y);
       const double ai = ky.y - (sre * y.y + sim * y.x);
-      const double uu = st[k * RR + jr], vv = st[(q2 + k) * RR + jr];
-      const double gr = fma(al.x * itau * itau, uu, vv * itau);
-      const double gi = al.y * itau * itau * uu;
+      const double x1 = st[k * RR + jr], x2 = st[(q2 + k) * RR + jr];
+      const double x3 = SW ? st[(2 * q2 + k) * RR + jr] : 0.0;
+      const double gr = fma(pc.k1.x, x1, fma(pc.k2.x, x2, pc.k3.x * x3));
+      const double gi = fma(pc.k1.y, x1, fma(pc.k2.y, x2, pc.k3.y * x3));
       gres[(long long)k * r + jr] = make_float2((float)(gr - ar), (float)(gi - ai));
     }
     // outward normal derivative at the edge slots: sx D[0 or p-1][.] along the row,
@@ -154,34 +178,82 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a, int RR) {
         v.x += Dr[l] * u.x;
         v.y += Dr[l] * u.y;
       }
-      dn[(long long)k * r + jr] = make_double2(sc * v.x, sc * v.y);
+      double2 out = make_double2(sc * v.x, sc * v.y);
+      if constexpr (SW) {
+        const int kw = a.slot_wall[L.vec_off + k];
+        if (kw >= 0) {   // wall row: rhs_b - (a d_n y - f d_t y)
+          // t = (-n2, n1): left -d_y, right +d_y, bottom +d_x, top -d_x
+          const double tsc = (s == 0) ? -a.sy : (s == 1) ? a.sy : (s == 2) ? a.sx : -a.sx;
+          double2 dt = make_double2(0.0, 0.0);
+          for (int l = 0; l < q; ++l) {
+            const int node = (s == 0) ? p * (l + 1) : (s == 1) ? (p - 1) + p * (l + 1)
+                           : (s == 2) ? (l + 1) : (l + 1) + p * (p - 1);
+            const double2 u = U[node * RR + jr];
+            const double d = a.Dq[t * q + l];
+            dt.x += d * u.x;
+            dt.y += d * u.y;
+          }
+          dt.x *= tsc;
+          dt.y *= tsc;
+          const double ax = al.x * itau, ay = al.y * itau;
+          const double* wv = a.wallv + (long long)(r0 + jr) * 2 * a.n_wall;
+          const double nv = wv[kw] * itau * a.inv_c, tv = wv[a.n_wall + kw] * itau * a.inv_c;
+          const double rr = ax * nv - a.f * tv - (ax * out.x - ay * out.y - a.f * dt.x);
+          const double ri = ay * nv - (ax * out.y + ay * out.x - a.f * dt.y);
+          out = make_double2(rr, ri);
+        }
+      }
+      dn[(long long)k * r + jr] = out;
+    }
+  }
+  if constexpr (SW) {   // first-sweep pole sums on the full grid
+    const long long plane = (long long)a.n_leaf * pp;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int idx = threadIdx.x + u * kBlock;
+      if (idx < RR * pp) {
+        const int node = idx / RR, jr = idx - node * RR;
+        if (r0 + jr < r) {
+          double* E = a.esum + (long long)(r0 + jr) * 3 * plane + (long long)leaf * pp + node;
+          E[0] = e0[u];
+          E[plane] = e1[u];
+          E[2 * plane] = e2[u];
+        }
+      }
     }
   }
 }
 
 // Bytes of LDS for RR right-hand sides per block.
-static size_t residual_lds(int p, int RR) {
+static size_t residual_lds(int p, int RR, int nsrc) {
   const int pp = p * p, q2 = (p - 2) * (p - 2);
-  return sizeof(double) * (2 * (size_t)pp + 2 * (size_t)q2 * p + 2 * (size_t)RR * q2) +
+  return sizeof(double) * (2 * (size_t)pp + 2 * (size_t)q2 * p + (size_t)nsrc * RR * q2) +
          sizeof(double2) * (size_t)RR * pp;
 }
 
-hipError_t launch_residual(const ResidualArgs& a, int n_leaf, hipStream_t s) {
+template <bool SW>
+static hipError_t residual_t(const ResidualArgs& a, int n_leaf, hipStream_t s) {
   // right-hand sides per block: up to 32, within 56 KiB of LDS (two to
-  // three blocks per CU), at least 1 (then up to 160 KiB)
+  // three blocks per CU), at least 1 (then up to 160 KiB); the grid values
+  // of one pole are at most 8 per thread
   int RR = 32;
-  while (RR > 1 && (RR / 2 >= a.nrhs || residual_lds(a.p, RR) > 56 * 1024 ||
+  while (RR > 1 && (RR / 2 >= a.nrhs || residual_lds(a.p, RR, a.nsrc) > 56 * 1024 ||
                     RR * a.p * a.p > 8 * kBlock))
     RR /= 2;
-  const size_t lds = residual_lds(a.p, RR);
+  const size_t lds = residual_lds(a.p, RR, a.nsrc);
   if (lds > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_residual),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_residual<SW>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   const int nrg = (a.nrhs + RR - 1) / RR;
-  hipLaunchKernelGGL(k_residual, dim3(n_leaf * nrg), dim3(kBlock), lds, s, a, RR);
+  hipLaunchKernelGGL(k_residual<SW>, dim3(n_leaf * nrg), dim3(kBlock), lds, s, a, RR);
   return hipGetLastError();
+}
+
+hipError_t launch_residual(const ResidualArgs& a, int n_leaf, hipStream_t s) {
+  if (a.esum) return residual_t<true>(a, n_leaf, s);
+  return residual_t<false>(a, n_leaf, s);
 }
 
 }  // namespace hx

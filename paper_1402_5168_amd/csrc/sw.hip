@@ -15,7 +15,8 @@
 // after the sweeps:
 //   k_sw_post   the pole sums E0 = sum b eta, E1 = sum b (a/s) eta,
 //               E2 = sum b eta/s on each element's full grid (interior from
-//               the leaf sweep, edges from the merge sweep), then
+//               the leaf sweep, edges from the merge sweep; in the precision
+//               form added to the first sweep's sums), then
 //               eta' = E0,
 //               v' = c grad(E1) - c f J grad(E2) - (beta1 v0 - f beta2 J v0)/tau,
 //               with beta1 = sum b a/s, beta2 = sum b/s (all m); grad uses the
@@ -104,7 +105,13 @@ __global__ __launch_bounds__(kBlock) void k_sw_post(SwPostArgs<T> a) {
   double* Ds = smem;                  // p x p
   double* E = Ds + pp;                // [3][p*p]: E0, E1, E2 on the full grid
   for (int t = threadIdx.x; t < pp; t += blockDim.x) Ds[t] = a.D[t];
-  for (int t = threadIdx.x; t < 3 * pp; t += blockDim.x) E[t] = 0.0;
+  // precision form: start from the first sweep's sums (FP64)
+  const long long plane = (long long)a.n_leaf * pp;
+  const double* es = a.esum ? a.esum + (long long)rhs * 3 * plane + (long long)leaf * pp : nullptr;
+  for (int t = threadIdx.x; t < 3 * pp; t += blockDim.x) {
+    const int fld = t / pp, node = t - fld * pp;
+    E[t] = es ? es[fld * plane + node] : 0.0;
+  }
   __syncthreads();
   // interior nodes: sum over poles of the leaf sweep's solutions
   for (int k = threadIdx.x; k < q2; k += blockDim.x) {
@@ -118,9 +125,9 @@ __global__ __launch_bounds__(kBlock) void k_sw_post(SwPostArgs<T> a) {
       s1 += c.c1.x * double(y.x) - c.c1.y * double(y.y);
       s2 += c.c2.x * double(y.x) - c.c2.y * double(y.y);
     }
-    E[node] = s0;
-    E[pp + node] = s1;
-    E[2 * pp + node] = s2;
+    E[node] += s0;
+    E[pp + node] += s1;
+    E[2 * pp + node] += s2;
   }
   // edge nodes (all four sides carry exterior values)
   for (int k = threadIdx.x; k < L.e; k += blockDim.x) {
@@ -140,9 +147,9 @@ __global__ __launch_bounds__(kBlock) void k_sw_post(SwPostArgs<T> a) {
       s1 += c.c1.x * double(y.x) - c.c1.y * double(y.y);
       s2 += c.c2.x * double(y.x) - c.c2.y * double(y.y);
     }
-    E[node] = s0;
-    E[pp + node] = s1;
-    E[2 * pp + node] = s2;
+    E[node] += s0;
+    E[pp + node] += s1;
+    E[2 * pp + node] += s2;
   }
   __syncthreads();
   double* st = a.state + rhs * a.rhs_stride + (long long)L.elem * q2;

@@ -2,7 +2,8 @@
 CPU oracle (oracle/shallow_water.py), through the C-ABI.
 
 Tolerance: relative L-infinity error per field <= 1e-10 after the stated
-number of steps (FP64 form).  The cases cover square and ragged meshes,
+number of steps (FP64 form), <= 1e-7 for the precision form (FP32 sweeps
+with one FP64 residual correction per step).  The cases cover square and ragged meshes,
 f = 0 and f != 0, several right-hand sides (one and two tiles of 16), a
 stretched domain, and a plan holding a wave and a shallow-water instance.
 """
@@ -48,10 +49,10 @@ def oracle_run(w, n_steps):
     return [st.run(w.v1[k], w.v2[k], w.eta[k], n_steps) for k in range(w.v1.shape[0])]
 
 
-def gpu_run(ws, n_steps, extra_wave=None):
+def gpu_run(ws, n_steps, extra_wave=None, precision=0):
     torch = _torch()
     from paper_1402_5168_amd import hpsexp
-    plan = hpsexp.Plan(device=0)
+    plan = hpsexp.Plan(device=0, precision=precision)
     for w in ws:
         m, r = w.mesh, w.recipe
         plan.add_sw(m.nex, m.ney, m.p, r.f, r.gH, w.tau, 1e-10, w.fit.alpha, w.fit.b,
@@ -116,3 +117,14 @@ def test_sw_beside_wave_instance():
     alone = gpu_run([w], 3)[0]
     assert np.array_equal(both[0], alone)
     check(w, alone, 3)
+
+
+@pytest.mark.parametrize("nex,ney,p,npoles,n_rhs,f,steps",
+                         [(2, 2, 8, 21, 1, 1.0, 5), (4, 4, 12, 21, 3, 1.0, 5),
+                          (1, 1, 6, 21, 2, 0.0, 5), (4, 2, 10, 41, 20, 2.0, 3),
+                          (8, 8, 6, 21, 5, 1.0, 3)])
+def test_sw_precision_form(nex, ney, p, npoles, n_rhs, f, steps):
+    say(f"sw fp32+refine {nex}x{ney} p={p} {npoles} poles nrhs={n_rhs} f={f} steps={steps}")
+    w = make(nex, ney, p, npoles=npoles, n_rhs=n_rhs, f=f)
+    got = gpu_run([w], steps, precision=1)[0]
+    check(w, got, steps, tol=1e-7)
