@@ -38,9 +38,12 @@ FP64_PEAK_TFLOPS = 78.6       # MI355X dense FP64 (vector and matrix)
 FP32_PEAK_TFLOPS = 157.3      # MI355X dense FP32 (vector and matrix)
 
 
-def interface_nodes(mesh) -> int:
-    """Sum over elements of their non-boundary edge nodes."""
+def interface_nodes(mesh, walls: bool = False) -> int:
+    """Sum over elements of their edge nodes that are unknowns (interfaces;
+    with slip walls also the wall nodes)."""
     sides = 2 * ((mesh.nex - 1) * mesh.ney + mesh.nex * (mesh.ney - 1))
+    if walls:
+        sides += 2 * (mesh.nex + mesh.ney)
     return sides * mesh.q
 
 
@@ -51,7 +54,7 @@ def leaf_up_flops(mesh, npole: int, nrhs: int) -> float:
     return 8.0 * mesh.n_el * q2 * q2 * npole * nrhs
 
 
-def algorithmic_bytes(mesh, npole: int, nrhs: int) -> dict:
+def algorithmic_bytes(mesh, npole: int, nrhs: int, sw: bool = False) -> dict:
     """Bytes each kernel class must move per launch (all columns).
 
     k_leaf_up: W (q^4 complex) per element and column, the state read once
@@ -61,13 +64,51 @@ def algorithmic_bytes(mesh, npole: int, nrhs: int) -> dict:
     read and written once."""
     q2 = mesh.q * mesh.q
     ncol = npole * nrhs
-    E = interface_nodes(mesh)
+    E = interface_nodes(mesh, sw)
     c16, d8 = 16, 8
     leaf_up = ncol * (mesh.n_el * q2 * q2 * c16 + mesh.n_el * q2 * c16 + E * c16) \
         + nrhs * 2 * mesh.n_el * q2 * d8
     leaf_down = ncol * (q2 * E * c16 + E * c16 + 2 * mesh.n_el * q2 * c16)
     pole_sum = ncol * mesh.n_el * q2 * c16 + nrhs * 3 * mesh.n_el * q2 * d8
     return {"k_leaf_up": leaf_up, "k_leaf_down": leaf_down, "k_pole_sum": pole_sum}
+
+
+def cpu_baseline_sw(recipe, npole_folded: int, sub: int = 8, poles: int = 4,
+                    min_seconds: float = 10.0):
+    """As cpu_baseline, for shallow water: the oracle's resolvent (sources,
+    sparse solve of the eta system, velocity recovery) for `poles` of the
+    folded shifts on a sub-mesh, scaled to all folded poles."""
+    import numpy as np
+
+    from oracle import shallow_water as osw
+    from workloads import configs
+
+    rec = configs.scaled_sw(recipe, sub, sub)
+    w = configs.make_sw(rec, n_rhs=1)
+    m = w.mesh
+    g = osw.SWGrid(m.nex, m.ney, m.p)
+    M = w.fit.M
+    picks = np.linspace(0, M, poles).round().astype(int)
+    steppers = [osw.SWStepper(g, rec.f, rec.gH, w.tau, w.fit.alpha[M + k:M + k + 1],
+                              w.fit.b[M + k:M + k + 1]) for k in picks]
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        for st in steppers:
+            st.resolvent(0, w.v1[0], w.v2[0], w.eta[0])
+        reps += 1
+        if time.perf_counter() - t0 >= min_seconds or reps >= 100000:
+            break
+    dt = (time.perf_counter() - t0) / (reps * poles)
+    step_s = dt * npole_folded
+    dof = 3 * m.n_el * m.q * m.q
+    return {"value": dof / step_s, "unit": "DOF·steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{sub}x{sub}-element sub-mesh, same p, f and gH, {poles} of "
+                       f"{npole_folded} folded poles (sparse LU factorisation excluded), "
+                       f"{reps} resolvent applications each ({dt * 1e3:.2f} ms each), scaled "
+                       f"to {npole_folded} poles and one right-hand side; the SuperLU solve "
+                       f"is single-threaded"),
+            "step_seconds_sample": step_s}
 
 
 def cpu_baseline(recipe, npole_folded: int, sub: int = 8, poles: int = 4,
@@ -122,12 +163,18 @@ def run(w, precision: str, unbatched: bool, steps: int, warmup: int, profile: bo
     from workloads import configs
 
     m = w.mesh
-    nrhs = w.u0.shape[0]
+    sw = isinstance(w, configs.SWInputs)
+    nrhs = w.state().shape[0]
     fp32 = precision == "fp32-refine"
-    batched = fp32 or (nrhs > 1 and not unbatched)
+    batched = fp32 or sw or (nrhs > 1 and not unbatched)
     plan = hpsexp.Plan(device=0, flags=hpsexp.HX_FLAG_UNBATCHED if unbatched else 0,
                        precision=hpsexp.HX_FP32_REFINE if fp32 else hpsexp.HX_FP64)
-    plan.add(m.nex, m.ney, m.p, w.c2, w.tau, configs.DELTA, w.fit.alpha, w.fit.b, nrhs=nrhs)
+    if sw:
+        plan.add_sw(m.nex, m.ney, m.p, w.recipe.f, w.recipe.gH, w.tau, configs.DELTA,
+                    w.fit.alpha, w.fit.b, nrhs=nrhs)
+    else:
+        plan.add(m.nex, m.ney, m.p, w.c2, w.tau, configs.DELTA, w.fit.alpha, w.fit.b,
+                 nrhs=nrhs)
     info = plan.query()
     plan.bind()
     torch.cuda.synchronize()
@@ -165,7 +212,7 @@ def run(w, precision: str, unbatched: bool, steps: int, warmup: int, profile: bo
            "build_s": build_s, "batched": batched, "info": info}
     if profile:
         kernels = {}
-        ab = algorithmic_bytes(m, info["folded_poles"], nrhs)
+        ab = algorithmic_bytes(m, info["folded_poles"], nrhs, sw)
         for k, name in enumerate(hpsexp.KERNEL_NAMES):
             if nl[k] == 0:
                 continue
@@ -202,7 +249,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="wave_64x64_p10")
+    ap.add_argument("--workload", default="wave_64x64_p10",
+                    help="wave_4x4_p12, wave_32x32_p16, wave_64x64_p10 or sw_32x32_p12")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP64 runs of the same workload")
@@ -221,10 +269,16 @@ def main():
 
     from workloads import configs
 
-    rec = configs.RECIPES[args.workload]
-    w = configs.make(rec, n_rhs=args.nrhs)
+    sw = args.workload in configs.SW_RECIPES
+    if sw:
+        rec = configs.SW_RECIPES[args.workload]
+        w = configs.make_sw(rec, n_rhs=args.nrhs)
+    else:
+        rec = configs.RECIPES[args.workload]
+        w = configs.make(rec, n_rhs=args.nrhs)
     m = w.mesh
-    nrhs = w.u0.shape[0]
+    nrhs = w.state().shape[0]
+    nfield = 3 if sw else 2
     head, final = run(w, args.precision, args.unbatched, args.steps, args.warmup)
     info = head["info"]
     out = {
@@ -233,7 +287,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if args.precision == "fp32-refine" else "f64",
         "data": "synthetic",
-        "config": {"workload": rec.name, "elements": f"{m.nex}x{m.ney}", "p": m.p,
+        "config": {"workload": rec.name, "problem": "shallow water, slip walls" if sw else
+                   "wave, Dirichlet", "elements": f"{m.nex}x{m.ney}", "p": m.p,
                    "poles": rec.npoles, "folded_poles": info["folded_poles"], "nrhs": nrhs,
                    "precision": args.precision, "batched_rhs": head["batched"],
                    "tau": w.tau, "dof_state": info["dof_state"],
@@ -251,10 +306,10 @@ def main():
         ref, ref_final = run(w, "fp64", False, args.steps, args.warmup, profile=False)
         err = 0.0
         for r in range(nrhs):
-            for f in range(2):
+            for f in range(nfield):
                 x, y = final[r, f], ref_final[r, f]
                 err = max(err, float(np.abs(x - y).max() / np.abs(y).max()))
-        w1 = configs.make(rec, n_rhs=1)
+        w1 = configs.make_sw(rec, n_rhs=1) if sw else configs.make(rec, n_rhs=1)
         one, _ = run(w1, "fp64", False, max(args.steps // 2, 1), 1, profile=False)
         out["compare"] = {
             "rel_err_vs_fp64": err,
@@ -264,7 +319,7 @@ def main():
             "speedup_vs_fp64_batched": head["value"] / ref["value"],
         }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(rec, info["folded_poles"])
+        out["cpu_baseline"] = (cpu_baseline_sw if sw else cpu_baseline)(rec, info["folded_poles"])
     print(json.dumps(out), flush=True)
 
 

@@ -47,12 +47,40 @@ __device__ __forceinline__ float2 ld_stream(const float2* p) {
   return make_float2(v.x, v.y);
 }
 
+// Accumulators of one wave's 16-row tile.  FP32 tiles also keep FP64
+// running sums: the MFMA accumulates a group of k-steps in FP32, then
+// flush() adds the group into FP64, so the rounding error does not grow
+// with the depth of long products (merge operators reach k ~ 10^3).
 template <class T, int NT>
 struct Acc {
+  static constexpr bool kWide = sizeof(T) == sizeof(float);
+  typedef double d4 __attribute__((ext_vector_type(4)));
   typename MM<T>::v4 re[NT], im[NT];
+  d4 re64[NT], im64[NT];
   __device__ void zero() {
     for (int t = 0; t < NT; ++t)
-      for (int v = 0; v < 4; ++v) re[t][v] = im[t][v] = T(0);
+      for (int v = 0; v < 4; ++v) {
+        re[t][v] = im[t][v] = T(0);
+        re64[t][v] = im64[t][v] = 0.0;
+      }
+  }
+  __device__ void flush() {
+    if constexpr (kWide) {
+      for (int t = 0; t < NT; ++t)
+        for (int v = 0; v < 4; ++v) {
+          re64[t][v] += double(re[t][v]);
+          im64[t][v] += double(im[t][v]);
+          re[t][v] = im[t][v] = T(0);
+        }
+    }
+  }
+  __device__ double vre(int t, int v) const {
+    if constexpr (kWide) return re64[t][v] + double(re[t][v]);
+    else return re[t][v];
+  }
+  __device__ double vim(int t, int v) const {
+    if constexpr (kWide) return im64[t][v] + double(im[t][v]);
+    else return im[t][v];
   }
 };
 
@@ -118,6 +146,7 @@ __device__ __forceinline__ void mm_chunk(Acc<T, NT>& acc, const typename MM<T>::
       mma_step<T, NT>(acc, a, Bk);
       Bk += bstep;
     }
+    acc.flush();
   }
 #pragma unroll
   for (int u = 0; u < PF; ++u)
@@ -125,6 +154,7 @@ __device__ __forceinline__ void mm_chunk(Acc<T, NT>& acc, const typename MM<T>::
       mma_step<T, NT>(acc, ring[u], Bk);
       Bk += bstep;
     }
+  acc.flush();
 }
 
 // Visit the wave's results: f(row, j, value) for row < nrows, j < RT.
@@ -139,8 +169,8 @@ __device__ __forceinline__ void mm_emit(const Acc<T, NT>& acc, int row0, int nro
       const int row = row0 + MM<T>::row(lane, v);
       if (row < nrows) {
         C c;
-        c.x = acc.re[t][v];
-        c.y = acc.im[t][v];
+        c.x = T(acc.vre(t, v));
+        c.y = T(acc.vim(t, v));
         f(row, t * 16 + (lane & 15), c);
       }
     }
@@ -452,8 +482,8 @@ __global__ __launch_bounds__(kBlock) void k_leaf_down_sum_mm(MmLeafDownArgs<T> a
           const int rhs = rt * RT + t * 16 + (lane & 15);
           if (row < q2 && rhs < r) {
             const C wv = w[(long long)row * r + rhs];
-            double yr = double(wv.x) - double(acc.re[t][v]);
-            double yi = double(wv.y) - double(acc.im[t][v]);
+            double yr = double(wv.x) - acc.vre(t, v);
+            double yi = double(wv.y) - acc.vim(t, v);
             if (y0) {  // corrected solution of the precision form
               const C y0v = y0[(long long)row * r + rhs];
               yr += double(y0v.x);

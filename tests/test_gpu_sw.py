@@ -128,3 +128,65 @@ def test_sw_precision_form(nex, ney, p, npoles, n_rhs, f, steps):
     w = make(nex, ney, p, npoles=npoles, n_rhs=n_rhs, f=f)
     got = gpu_run([w], steps, precision=1)[0]
     check(w, got, steps, tol=1e-7)
+
+
+def _full_size_run(f, first_states, n_steps, precision=1):
+    """The 32x32 p=12, 101-pole, 64-state workload in the launch form the
+    benchmark times; the first right-hand sides are replaced by the given
+    states.  Returns (inputs, final states)."""
+    rec = dataclasses.replace(configs.SW_RECIPES["sw_32x32_p12"], f=f)
+    w = configs.make_sw(rec)
+    for k, (v1, v2, eta) in enumerate(first_states):
+        w.v1[k], w.v2[k], w.eta[k] = v1, v2, eta
+    return w, gpu_run([w], n_steps, precision=precision)[0]
+
+
+# Bound after 10 steps: FP64, ten times the fit's per-step error delta = 1e-10
+# (the spatial discretisation error of these smooth states is far smaller);
+# precision form, the 1e-7 relative bar set for it.
+FULL_TOL = {0: 1e-8, 1: 1e-7}
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_geostrophic_state_is_steady(precision):
+    """f = 1: eta = sin(pi x) sin(pi y), v = -(c/f) J grad(eta) is a steady
+    state of the slip-wall problem; after 10 steps it must be unchanged to
+    the bound above.  The other 63 states must stay finite and bounded
+    (|R| <= 1)."""
+    say(f"sw_32x32_p12 full size, precision {precision}, 64 RHS, geostrophic state, 10 steps")
+    m = configs.SW_RECIPES["sw_32x32_p12"].mesh
+    X, Y = layout.interior_nodes(m)
+    eta = np.sin(np.pi * X) * np.sin(np.pi * Y)
+    v1 = -np.pi * np.sin(np.pi * X) * np.cos(np.pi * Y)      # -(c/f) d_y eta
+    v2 = np.pi * np.cos(np.pi * X) * np.sin(np.pi * Y)       # (c/f) d_x eta
+    w, got = _full_size_run(1.0, [(v1, v2, eta)], 10, precision)
+    for fi, x in enumerate((v1, v2, eta)):
+        e = rel_err(got[0, fi], x)
+        say(f"field {fi}: rel change {e:.3e}")
+        assert e <= FULL_TOL[precision], (fi, e)
+    assert np.isfinite(got).all()
+    assert np.abs(got[1:]).max() <= 3.0 * np.abs(w.state()[1:]).max()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_neumann_mode_f0_closed_form(precision):
+    """f = 0: eta0 = cos(k pi x) cos(l pi y), v0 = 0 evolves as
+    eta = cos(w t) eta0, v = (c/w) sin(w t) grad(eta0), w = c pi |k|."""
+    say(f"sw_32x32_p12 full size with f=0, precision {precision}, 64 RHS, mode (3,2), 10 steps")
+    m = configs.SW_RECIPES["sw_32x32_p12"].mesh
+    X, Y = layout.interior_nodes(m)
+    k, l = 3, 2
+    eta0 = np.cos(k * np.pi * X) * np.cos(l * np.pi * Y)
+    zero = np.zeros_like(eta0)
+    w, got = _full_size_run(0.0, [(zero, zero, eta0)], 10, precision)
+    t = 10 * w.tau
+    om = np.pi * np.hypot(k, l)
+    eta = np.cos(om * t) * eta0
+    gx = -k * np.pi * np.sin(k * np.pi * X) * np.cos(l * np.pi * Y)
+    gy = -l * np.pi * np.cos(k * np.pi * X) * np.sin(l * np.pi * Y)
+    v1, v2 = np.sin(om * t) / om * gx, np.sin(om * t) / om * gy
+    scale = max(np.abs(eta0).max(), np.abs(gx).max() / om)
+    for fi, x in enumerate((v1, v2, eta)):
+        e = np.abs(got[0, fi] - x).max() / scale
+        say(f"field {fi}: error {e:.3e} of the mode's amplitude")
+        assert e <= FULL_TOL[precision], (fi, e)
