@@ -187,7 +187,7 @@ struct SwPostArgs {
   long long rhs_stride;
   int n_int;
   double sx, sy, c, f, beta1, beta2, inv_tau;
-  const double* esum;        // precision form: first-sweep sums [rhs][3][leaf][p*p] (null: none)
+  const double* esum;        // precision form: first-sweep sums [leaf][3][p*p][rhs] (null: none)
   int n_leaf;
 };
 
@@ -241,7 +241,7 @@ struct ResidualArgs {
   const double* Dq;          // q x q interior-line differentiation
   double f, inv_c;
   const SwCoef* swc;
-  double* esum;              // first-sweep pole sums E0, E1, E2 [rhs][3][leaf][p*p]
+  double* esum;              // first-sweep pole sums E0, E1, E2 [leaf][3][p*p][rhs]
 };
 hipError_t launch_residual(const ResidualArgs& a, int n_leaf, hipStream_t s);
 

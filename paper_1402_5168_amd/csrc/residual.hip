@@ -37,8 +37,14 @@ __device__ __forceinline__ int side_of_slot_r(int mask, int slot) {
 
 template <bool SW>
 __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a, int RR) {
+  // Work items are rhs-fastest (RR is a power of two).  Each thread fetches
+  // the same kPer grid items (node, rhs) for every pole (RR p^2 <= kPer
+  // kBlock), with offsets computed once; the interior rows and edge slots
+  // look their node indices up in small LDS tables.
+  constexpr int kPer = 8;
   extern __shared__ double sm[];
   const int p = a.p, q = a.q, q2 = q * q, pp = p * p;
+  const int lg = __ffs(RR) - 1;
   const int nrg = (a.nrhs + RR - 1) / RR;
   const int rg = blockIdx.x % nrg;
   const int leaf = blockIdx.x / nrg;
@@ -54,12 +60,21 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a, int RR) {
   const int ns = a.nsrc;
   double* st = My + q2 * p;                           // sources: [nsrc][q*q][RR]
   double2* U = reinterpret_cast<double2*>(st + ns * RR * q2);   // grid values [p*p][RR]
+  int* kij = reinterpret_cast<int*>(U + RR * pp);     // interior k -> i | jj << 8
+  int* dmt = kij + q2;                                // edge slot k -> side | t << 2 | (wall+1) << 8
   for (int t = threadIdx.x; t < pp; t += blockDim.x) {
     Ds[t] = a.D[t];
     cs[t] = a.c2[(long long)L.elem * pp + t];
   }
+  for (int k = threadIdx.x; k < q2; k += blockDim.x) kij[k] = (k % q + 1) | ((k / q + 1) << 8);
+  for (int k = threadIdx.x; k < L.e; k += blockDim.x) {
+    const int slot = k / q, t = k - slot * q;
+    int kw = -1;
+    if constexpr (SW) kw = a.slot_wall[L.vec_off + k];
+    dmt[k] = side_of_slot_r(L.side_mask, slot) | (t << 2) | ((kw + 1) << 8);
+  }
   for (int idx = threadIdx.x; idx < RR * ns * q2; idx += blockDim.x) {
-    const int k = idx / RR, jr = idx - k * RR;        // k < nsrc q^2: field-major
+    const int k = idx >> lg, jr = idx & (RR - 1);     // k < nsrc q^2: field-major
     const int fld = k / q2, kk = k - fld * q2;
     const int rhs = r0 + jr;
     st[idx] = (rhs < r) ? a.state[rhs * a.rhs_stride + (long long)fld * a.n_int +
@@ -79,32 +94,39 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a, int RR) {
     Mx[((jj - 1) * q + (i - 1)) * p + l] = sx2 * mx;
     My[((i - 1) * q + (jj - 1)) * p + l] = sy2 * my;
   }
-  const double itau = 1.0 / a.tau;
-  // grid values of one pole, fetched a pole ahead into registers (at most
-  // kPer per thread) so their HBM latency overlaps the previous pole's work
-  constexpr int kPer = 8;
-  auto fetch = [&](int pole, float2* buf) {
-    const float2* y0 = a.y0 + ((long long)pole * a.w_pole + (long long)leaf * q2) * r + r0;
-    const float2* ue = a.ue + ((long long)pole * a.e_pole + L.vec_off) * r + r0;
+  // fetch offsets: >= 0 interior (y0), < -1 edge (ue at -2-off), -1 none
+  int off[kPer];
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int idx = threadIdx.x + u * kBlock;
-      float2 v = make_float2(0.f, 0.f);
-      if (idx < RR * pp) {
-        const int node = idx / RR, jr = idx - node * RR;
-        const int i = node % p, jj = node / p;
-        if (r0 + jr < r) {
-          const bool ix = (i > 0 && i < p - 1), iy = (jj > 0 && jj < p - 1);
-          if (ix && iy) {
-            v = y0[(long long)((i - 1) + q * (jj - 1)) * r + jr];
-          } else if (ix != iy) {  // non-corner edge node
-            const int s = (i == 0) ? 0 : (i == p - 1) ? 1 : (jj == 0) ? 2 : 3;
-            const int t = (s < 2) ? jj - 1 : i - 1;
-            const int sl = slot_of_side(L.side_mask, s);
-            if (sl >= 0) v = ue[(long long)(sl * q + t) * r + jr];
-          }
+  for (int u = 0; u < kPer; ++u) {
+    const int idx = threadIdx.x + u * kBlock;
+    off[u] = -1;
+    if (idx < RR * pp) {
+      const int node = idx >> lg, jr = idx & (RR - 1);
+      const int i = node % p, jj = node / p;
+      if (r0 + jr < r) {
+        const bool ix = (i > 0 && i < p - 1), iy = (jj > 0 && jj < p - 1);
+        if (ix && iy) {
+          off[u] = ((i - 1) + q * (jj - 1)) * r + jr;
+        } else if (ix != iy) {  // non-corner edge node
+          const int sd = (i == 0) ? 0 : (i == p - 1) ? 1 : (jj == 0) ? 2 : 3;
+          const int t = (sd < 2) ? jj - 1 : i - 1;
+          const int sl = slot_of_side(L.side_mask, sd);
+          if (sl >= 0) off[u] = -2 - ((sl * q + t) * r + jr);
         }
       }
+    }
+  }
+  const double itau = 1.0 / a.tau;
+  const float2* y0b = a.y0 + (long long)leaf * q2 * r + r0;
+  const float2* ueb = a.ue + (long long)L.vec_off * r + r0;
+  auto fetch = [&](int pole, float2* buf) {
+    const float2* y0 = y0b + (long long)pole * a.w_pole * r;
+    const float2* ue = ueb + (long long)pole * a.e_pole * r;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      float2 v = make_float2(0.f, 0.f);
+      if (off[u] >= 0) v = y0[off[u]];
+      else if (off[u] < -1) v = ue[-2 - off[u]];
       buf[u] = v;
     }
   };
@@ -138,21 +160,23 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a, int RR) {
     const double2 al = pc.alpha;
     const double sre = pc.sig.x, sim = pc.sig.y;
     float2* gres = a.gres + ((long long)pole * a.w_pole + (long long)leaf * q2) * r + r0;
-    for (int idx = threadIdx.x; idx < RR * q2; idx += blockDim.x) {
-      const int k = idx / RR, jr = idx - k * RR;
+    for (int idx = threadIdx.x; idx < RR * q2; idx += kBlock) {
+      const int jr = idx & (RR - 1), k = idx >> lg;
       if (r0 + jr >= r) continue;
-      const int i = k % q + 1, jj = k / q + 1;
+      const int ij = kij[k];
+      const int i = ij & 255, jj = ij >> 8;
       const double* mx = Mx + ((jj - 1) * q + (i - 1)) * p;
       const double* my = My + ((i - 1) * q + (jj - 1)) * p;
+      const double2* ux = U + (p * jj) * RR + jr;     // row jj, stride RR
+      const double2* uy = U + i * RR + jr;            // column i, stride p RR
       double2 ky = make_double2(0.0, 0.0);
       for (int l = 0; l < p; ++l) {
-        const double2 ux = U[(l + p * jj) * RR + jr];
-        const double2 uy = U[(i + p * l) * RR + jr];
-        ky.x += mx[l] * ux.x + my[l] * uy.x;
-        ky.y += mx[l] * ux.y + my[l] * uy.y;
+        const double2 a1 = ux[l * RR], a2 = uy[l * p * RR];
+        ky.x += mx[l] * a1.x + my[l] * a2.x;
+        ky.y += mx[l] * a1.y + my[l] * a2.y;
       }
       const double2 y = U[(i + p * jj) * RR + jr];
-      // (K - s) y
+      // (K - sigma) y
       const double ar = ky.x - (sre * y.x - sim * y.y);
       const double ai = ky.y - (sre * y.y + sim * y.x);
       const double x1 = st[k * RR + jr], x2 = st[(q2 + k) * RR + jr];
@@ -164,34 +188,39 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a, int RR) {
     // outward normal derivative at the edge slots: sx D[0 or p-1][.] along the row,
     // sy D[0 or p-1][.] along the column
     double2* dn = a.dn + ((long long)pole * a.e_pole + L.vec_off) * r + r0;
-    for (int idx = threadIdx.x; idx < RR * L.e; idx += blockDim.x) {
-      const int k = idx / RR, jr = idx - k * RR;
+    for (int idx = threadIdx.x; idx < RR * L.e; idx += kBlock) {
+      const int jr = idx & (RR - 1), k = idx >> lg;
       if (r0 + jr >= r) continue;
-      const int slot = k / q, t = k - slot * q;
-      const int s = side_of_slot_r(L.side_mask, slot);
-      const bool xn = s < 2, lo = (s == 0 || s == 2);
+      const int dmk = dmt[k];
+      const int sd = dmk & 3, t = (dmk >> 2) & 63;
+      const bool xn = sd < 2, lo = (sd == 0 || sd == 2);
       const double* Dr = Ds + (lo ? 0 : (p - 1)) * p;
       const double sc = xn ? (lo ? -a.sx : a.sx) : (lo ? -a.sy : a.sy);
+      const double2* ul = xn ? U + (p * (t + 1)) * RR + jr : U + (t + 1) * RR + jr;
+      const int ls = xn ? RR : p * RR;
       double2 v = make_double2(0.0, 0.0);
       for (int l = 0; l < p; ++l) {
-        const double2 u = xn ? U[(l + p * (t + 1)) * RR + jr] : U[((t + 1) + p * l) * RR + jr];
-        v.x += Dr[l] * u.x;
-        v.y += Dr[l] * u.y;
+        const double2 uu = ul[l * ls];
+        v.x += Dr[l] * uu.x;
+        v.y += Dr[l] * uu.y;
       }
       double2 out = make_double2(sc * v.x, sc * v.y);
       if constexpr (SW) {
-        const int kw = a.slot_wall[L.vec_off + k];
+        const int kw = (dmk >> 8) - 1;
         if (kw >= 0) {   // wall row: rhs_b - (a d_n y - f d_t y)
           // t = (-n2, n1): left -d_y, right +d_y, bottom +d_x, top -d_x
-          const double tsc = (s == 0) ? -a.sy : (s == 1) ? a.sy : (s == 2) ? a.sx : -a.sx;
+          const double tsc = (sd == 0) ? -a.sy : (sd == 1) ? a.sy : (sd == 2) ? a.sx : -a.sx;
+          // the side's q non-corner nodes: (0|p-1, l+1) or (l+1, 0|p-1)
+          const double2* ut = (sd == 0) ? U + p * RR + jr
+                            : (sd == 1) ? U + (2 * p - 1) * RR + jr
+                            : (sd == 2) ? U + RR + jr : U + (p * (p - 1) + 1) * RR + jr;
+          const int ts = xn ? p * RR : RR;
           double2 dt = make_double2(0.0, 0.0);
           for (int l = 0; l < q; ++l) {
-            const int node = (s == 0) ? p * (l + 1) : (s == 1) ? (p - 1) + p * (l + 1)
-                           : (s == 2) ? (l + 1) : (l + 1) + p * (p - 1);
-            const double2 u = U[node * RR + jr];
+            const double2 uu = ut[l * ts];
             const double d = a.Dq[t * q + l];
-            dt.x += d * u.x;
-            dt.y += d * u.y;
+            dt.x += d * uu.x;
+            dt.y += d * uu.y;
           }
           dt.x *= tsc;
           dt.y *= tsc;
@@ -206,18 +235,17 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a, int RR) {
       dn[(long long)k * r + jr] = out;
     }
   }
-  if constexpr (SW) {   // first-sweep pole sums on the full grid
-    const long long plane = (long long)a.n_leaf * pp;
+  if constexpr (SW) {   // first-sweep pole sums on the full grid, [leaf][3][p*p][rhs]
+    double* E = a.esum + (long long)leaf * 3 * pp * r + r0;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int idx = threadIdx.x + u * kBlock;
       if (idx < RR * pp) {
-        const int node = idx / RR, jr = idx - node * RR;
+        const int node = idx >> lg, jr = idx & (RR - 1);
         if (r0 + jr < r) {
-          double* E = a.esum + (long long)(r0 + jr) * 3 * plane + (long long)leaf * pp + node;
-          E[0] = e0[u];
-          E[plane] = e1[u];
-          E[2 * plane] = e2[u];
+          E[(long long)node * r + jr] = e0[u];
+          E[(long long)(pp + node) * r + jr] = e1[u];
+          E[(long long)(2 * pp + node) * r + jr] = e2[u];
         }
       }
     }
@@ -228,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a, int RR) {
 static size_t residual_lds(int p, int RR, int nsrc) {
   const int pp = p * p, q2 = (p - 2) * (p - 2);
   return sizeof(double) * (2 * (size_t)pp + 2 * (size_t)q2 * p + (size_t)nsrc * RR * q2) +
-         sizeof(double2) * (size_t)RR * pp;
+         sizeof(double2) * (size_t)RR * pp + sizeof(int) * ((size_t)q2 + 4 * (p - 2));
 }
 
 template <bool SW>

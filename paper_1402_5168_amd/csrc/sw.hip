@@ -94,81 +94,125 @@ __global__ __launch_bounds__(kBlock) void k_sw_root_form(SwRootFormArgs a) {
   }
 }
 
+// Side (0 left, 1 right, 2 bottom, 3 top) -> position among the element's
+// edge slots, -1 when the side carries no exterior values.
+__device__ __forceinline__ int sw_slot_of_side(int mask, int side) {
+  return ((mask >> side) & 1) ? __popc(mask & ((1 << side) - 1)) : -1;
+}
+
+// block = (element, group of RR right-hand sides).  Phase 1: every thread
+// owns up to kPer (node, rhs) items of the element's full grid, rhs fastest
+// so that the pole values of RR consecutive right-hand sides are read
+// together, and sums them over the poles in registers (the next pole's
+// values are fetched before the current ones are added).  Phase 2: the
+// sums go to LDS, and every interior item forms the gradients along the
+// p-point lines and the new state.
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_sw_post(SwPostArgs<T> a) {
+__global__ __launch_bounds__(kBlock) void k_sw_post(SwPostArgs<T> a, int RR) {
+  using C = typename Cplx<T>::type;
+  constexpr int kPer = 8;
   extern __shared__ double smem[];
   const int p = a.p, q = a.q, q2 = q * q, pp = p * p;
-  const int leaf = blockIdx.x / a.nrhs;
-  const int rhs = blockIdx.x - leaf * a.nrhs;
+  const int nrg = (a.nrhs + RR - 1) / RR;
+  const int rg = blockIdx.x % nrg;
+  const int leaf = blockIdx.x / nrg;
+  const int r = a.nrhs, r0 = rg * RR, ES = RR + 1;
   const LeafDesc L = a.leaves[leaf];
-  const int r = a.nrhs;
   double* Ds = smem;                  // p x p
-  double* E = Ds + pp;                // [3][p*p]: E0, E1, E2 on the full grid
+  double* E = Ds + pp;                // [3][p*p][ES]: E0, E1, E2
   for (int t = threadIdx.x; t < pp; t += blockDim.x) Ds[t] = a.D[t];
-  // precision form: start from the first sweep's sums (FP64)
-  const long long plane = (long long)a.n_leaf * pp;
-  const double* es = a.esum ? a.esum + (long long)rhs * 3 * plane + (long long)leaf * pp : nullptr;
-  for (int t = threadIdx.x; t < 3 * pp; t += blockDim.x) {
-    const int fld = t / pp, node = t - fld * pp;
-    E[t] = es ? es[fld * plane + node] : 0.0;
+  const C* yb = a.y + (long long)leaf * q2 * r + r0;
+  const C* ub = a.ue + (long long)L.vec_off * r + r0;
+  int off[kPer];                      // >= 0: interior (y) offset; < -1: edge (ue) offset -2-off
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int idx = threadIdx.x + u * kBlock;
+    off[u] = -1;
+    if (idx < RR * pp) {
+      const int node = idx / RR, jr = idx - node * RR;
+      const int i = node % p, j = node / p;
+      if (r0 + jr < r) {
+        const bool ix = (i > 0 && i < p - 1), iy = (j > 0 && j < p - 1);
+        if (ix && iy) {
+          off[u] = ((i - 1) + q * (j - 1)) * r + jr;
+        } else if (ix != iy) {
+          const int sd = (i == 0) ? 0 : (i == p - 1) ? 1 : (j == 0) ? 2 : 3;
+          const int t = (sd < 2) ? j - 1 : i - 1;
+          const int sl = sw_slot_of_side(L.side_mask, sd);
+          if (sl >= 0) off[u] = -2 - ((sl * q + t) * r + jr);
+        }
+      }
+    }
+  }
+  auto fetch = [&](int pole, C* buf) {
+    const C* yp = yb + (long long)pole * a.y_pole * r;
+    const C* up = ub + (long long)pole * a.e_pole * r;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      C v;
+      v.x = v.y = T(0);
+      if (off[u] >= 0) v = yp[off[u]];
+      else if (off[u] < -1) v = up[-2 - off[u]];
+      buf[u] = v;
+    }
+  };
+  double e0[kPer], e1[kPer], e2[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) e0[u] = e1[u] = e2[u] = 0.0;
+  C cur[kPer], nxt[kPer];
+  fetch(0, nxt);
+  for (int pole = 0; pole < a.npole; ++pole) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) cur[u] = nxt[u];
+    if (pole + 1 < a.npole) fetch(pole + 1, nxt);
+    const SwCoef c = a.coef[pole];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const double yr = double(cur[u].x), yi = double(cur[u].y);
+      e0[u] += c.c0.x * yr - c.c0.y * yi;
+      e1[u] += c.c1.x * yr - c.c1.y * yi;
+      e2[u] += c.c2.x * yr - c.c2.y * yi;
+    }
+  }
+  // precision form: add the first sweep's sums [leaf][3][p*p][rhs]
+  const double* es = a.esum ? a.esum + (long long)leaf * 3 * pp * r + r0 : nullptr;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int idx = threadIdx.x + u * kBlock;
+    if (idx < RR * pp) {
+      const int node = idx / RR, jr = idx - node * RR;
+      double f0 = e0[u], f1 = e1[u], f2 = e2[u];
+      if (es && r0 + jr < r) {
+        f0 += es[(long long)node * r + jr];
+        f1 += es[(long long)(pp + node) * r + jr];
+        f2 += es[(long long)(2 * pp + node) * r + jr];
+      }
+      E[node * ES + jr] = f0;
+      E[(pp + node) * ES + jr] = f1;
+      E[(2 * pp + node) * ES + jr] = f2;
+    }
   }
   __syncthreads();
-  // interior nodes: sum over poles of the leaf sweep's solutions
-  for (int k = threadIdx.x; k < q2; k += blockDim.x) {
-    const int node = (k % q + 1) + p * (k / q + 1);
-    double s0 = 0, s1 = 0, s2 = 0;
-    for (int pole = 0; pole < a.npole; ++pole) {
-      const typename Cplx<T>::type y =
-          a.y[((long long)pole * a.y_pole + (long long)leaf * q2 + k) * r + rhs];
-      const SwCoef c = a.coef[pole];
-      s0 += c.c0.x * double(y.x) - c.c0.y * double(y.y);
-      s1 += c.c1.x * double(y.x) - c.c1.y * double(y.y);
-      s2 += c.c2.x * double(y.x) - c.c2.y * double(y.y);
-    }
-    E[node] += s0;
-    E[pp + node] += s1;
-    E[2 * pp + node] += s2;
-  }
-  // edge nodes (all four sides carry exterior values)
-  for (int k = threadIdx.x; k < L.e; k += blockDim.x) {
-    const int slot = k / q, t = k - slot * q;
-    int s = -1, seen = -1;
-    for (int m = 0; m < 4; ++m)
-      if ((L.side_mask >> m) & 1)
-        if (++seen == slot) { s = m; break; }
-    const int node = (s == 0) ? p * (t + 1) : (s == 1) ? (p - 1) + p * (t + 1)
-                   : (s == 2) ? (t + 1) : (t + 1) + p * (p - 1);
-    double s0 = 0, s1 = 0, s2 = 0;
-    for (int pole = 0; pole < a.npole; ++pole) {
-      const typename Cplx<T>::type y =
-          a.ue[((long long)pole * a.e_pole + L.vec_off + k) * r + rhs];
-      const SwCoef c = a.coef[pole];
-      s0 += c.c0.x * double(y.x) - c.c0.y * double(y.y);
-      s1 += c.c1.x * double(y.x) - c.c1.y * double(y.y);
-      s2 += c.c2.x * double(y.x) - c.c2.y * double(y.y);
-    }
-    E[node] += s0;
-    E[pp + node] += s1;
-    E[2 * pp + node] += s2;
-  }
-  __syncthreads();
-  double* st = a.state + rhs * a.rhs_stride + (long long)L.elem * q2;
-  for (int k = threadIdx.x; k < q2; k += blockDim.x) {
+  // interior items, node fastest (the state is [rhs][field][n_int])
+  const double c = a.c, f = a.f;
+  for (int idx = threadIdx.x; idx < RR * q2; idx += blockDim.x) {
+    const int jr = idx / q2, k = idx - jr * q2;
+    if (r0 + jr >= r) break;
     const int i = k % q + 1, j = k / q + 1;
     double e1x = 0, e1y = 0, e2x = 0, e2y = 0;
     for (int m = 0; m < p; ++m) {
       const double dx = Ds[i * p + m], dy = Ds[j * p + m];
-      e1x += dx * E[pp + m + p * j];
-      e2x += dx * E[2 * pp + m + p * j];
-      e1y += dy * E[pp + i + p * m];
-      e2y += dy * E[2 * pp + i + p * m];
+      e1x += dx * E[(pp + m + p * j) * ES + jr];
+      e2x += dx * E[(2 * pp + m + p * j) * ES + jr];
+      e1y += dy * E[(pp + i + p * m) * ES + jr];
+      e2y += dy * E[(2 * pp + i + p * m) * ES + jr];
     }
     e1x *= a.sx; e2x *= a.sx; e1y *= a.sy; e2y *= a.sy;
+    double* st = a.state + (long long)(r0 + jr) * a.rhs_stride + (long long)L.elem * q2;
     const double v1 = st[k], v2 = st[a.n_int + k];
-    const double c = a.c, f = a.f;
     st[k] = c * e1x - c * f * e2y - (a.beta1 * v1 - f * a.beta2 * v2) * a.inv_tau;
     st[a.n_int + k] = c * e1y + c * f * e2x - (a.beta1 * v2 + f * a.beta2 * v1) * a.inv_tau;
-    st[2 * a.n_int + k] = E[(i + p * j)];
+    st[2 * a.n_int + k] = E[(i + p * j) * ES + jr];
   }
 }
 
@@ -193,8 +237,13 @@ hipError_t launch_sw_root_form(const SwRootFormArgs& a, int chunk, hipStream_t s
 
 template <class T>
 hipError_t launch_sw_post(const SwPostArgs<T>& a, int n_leaf, hipStream_t s) {
-  const size_t lds = sizeof(double) * 4 * (size_t)a.p * a.p;
-  hipLaunchKernelGGL((k_sw_post<T>), dim3(n_leaf * a.nrhs), dim3(kBlock), lds, s, a);
+  // right-hand sides per block: a power of two up to 8, the grid items of
+  // one pole at most 8 per thread
+  int RR = 8;
+  while (RR > 1 && (RR / 2 >= a.nrhs || RR * a.p * a.p > 8 * kBlock)) RR /= 2;
+  const size_t lds = sizeof(double) * (size_t)a.p * a.p * (1 + 3 * (RR + 1));
+  const int nrg = (a.nrhs + RR - 1) / RR;
+  hipLaunchKernelGGL((k_sw_post<T>), dim3(n_leaf * nrg), dim3(kBlock), lds, s, a, RR);
   return hipGetLastError();
 }
 
