@@ -181,14 +181,14 @@ constexpr int kKC = 64;  // k-chunk of B staged in LDS
 // ---- leaf upward: g from the state, w = W g, h = N_i w ------------------------
 // block = (leaf, pole, rhs tile); every row tile of W is handled by the block.
 template <class T, int NT>
-__global__ __launch_bounds__(kBlock) void k_leaf_up_mm(MmLeafUpArgs<T> a) {
+__device__ __forceinline__ void leaf_up_body(const MmLeafUpArgs<T>& a, const int bid) {
   using C = typename MM<T>::C;
   constexpr int RT = 16 * NT, BST = RT + 1;
   extern __shared__ unsigned char smem[];
   C* gs = reinterpret_cast<C*>(smem);
   const int n_rt = (a.nrhs + RT - 1) / RT;
-  const int rt = blockIdx.x % n_rt;
-  const int lp = blockIdx.x / n_rt;
+  const int rt = bid % n_rt;
+  const int lp = bid / n_rt;
   const int pole = lp % a.npole, leaf = lp / a.npole;
   const int q = a.q, q2 = q * q, q2p = (q2 + 3) & ~3;
   const LeafDesc L = a.leaves[leaf];
@@ -252,15 +252,28 @@ __global__ __launch_bounds__(kBlock) void k_leaf_up_mm(MmLeafUpArgs<T> a) {
   }
 }
 
+template <class T, int NT>
+__global__ __launch_bounds__(kBlock) void k_leaf_up_mm(MmLeafUpArgs<T> a) {
+  leaf_up_body<T, NT>(a, blockIdx.x);
+}
+
+template <class T, int NT>
+__global__ __launch_bounds__(kBlock) void k_leaf_up_mm_multi(Multi<MmLeafUpArgs<T>> m) {
+  int i;
+  const int bid = m.locate(blockIdx.x, i);
+  const MmLeafUpArgs<T> a = m.args[i];
+  leaf_up_body<T, NT>(a, bid);
+}
+
 // ---- merge upward: g3 = h3a + h3b (- j3), h_par = [h1a; h2b] - Y g3 ----------
 // block = (box, pole, rhs tile, row group of 64 rows of Y)
 template <class T, int NT>
-__global__ __launch_bounds__(kBlock) void k_merge_up_mm(MmMergeArgs<T> a) {
+__device__ __forceinline__ void merge_up_body(const MmMergeArgs<T>& a, const int bid) {
   using C = typename MM<T>::C;
   constexpr int RT = 16 * NT, BST = RT + 1;
   __shared__ C Bs[kKC * BST];
   const int n_rt = (a.nrhs + RT - 1) / RT;
-  int rest = blockIdx.x;
+  int rest = bid;
   const int rg = rest % a.row_groups; rest /= a.row_groups;
   const int rt = rest % n_rt; rest /= n_rt;
   const int pole = rest % a.npole;
@@ -323,14 +336,27 @@ __global__ __launch_bounds__(kBlock) void k_merge_up_mm(MmMergeArgs<T> a) {
   });
 }
 
+template <class T, int NT>
+__global__ __launch_bounds__(kBlock) void k_merge_up_mm(MmMergeArgs<T> a) {
+  merge_up_body<T, NT>(a, blockIdx.x);
+}
+
+template <class T, int NT>
+__global__ __launch_bounds__(kBlock) void k_merge_up_mm_multi(Multi<MmMergeArgs<T>> m) {
+  int i;
+  const int bid = m.locate(blockIdx.x, i);
+  const MmMergeArgs<T> a = m.args[i];
+  merge_up_body<T, NT>(a, bid);
+}
+
 // ---- merge downward: u3 = -Z [u_ext; g3], scattered to the children --------
 template <class T, int NT>
-__global__ __launch_bounds__(kBlock) void k_merge_down_mm(MmMergeArgs<T> a) {
+__device__ __forceinline__ void merge_down_body(const MmMergeArgs<T>& a, const int bid) {
   using C = typename MM<T>::C;
   constexpr int RT = 16 * NT, BST = RT + 1;
   __shared__ C Bs[kKC * BST];
   const int n_rt = (a.nrhs + RT - 1) / RT;
-  int rest = blockIdx.x;
+  int rest = bid;
   const int rg = rest % a.row_groups; rest /= a.row_groups;
   const int rt = rest % n_rt; rest /= n_rt;
   const int pole = rest % a.npole;
@@ -389,14 +415,27 @@ __global__ __launch_bounds__(kBlock) void k_merge_down_mm(MmMergeArgs<T> a) {
   });
 }
 
+template <class T, int NT>
+__global__ __launch_bounds__(kBlock) void k_merge_down_mm(MmMergeArgs<T> a) {
+  merge_down_body<T, NT>(a, blockIdx.x);
+}
+
+template <class T, int NT>
+__global__ __launch_bounds__(kBlock) void k_merge_down_mm_multi(Multi<MmMergeArgs<T>> m) {
+  int i;
+  const int bid = m.locate(blockIdx.x, i);
+  const MmMergeArgs<T> a = m.args[i];
+  merge_down_body<T, NT>(a, bid);
+}
+
 // ---- leaf downward: y = w - S u_e (in place of w) -----------------------------
 template <class T, int NT>
-__global__ __launch_bounds__(kBlock) void k_leaf_down_mm(MmLeafDownArgs<T> a) {
+__device__ __forceinline__ void leaf_down_body(const MmLeafDownArgs<T>& a, const int bid) {
   using C = typename MM<T>::C;
   constexpr int RT = 16 * NT, BST = RT + 1;
   __shared__ C Bs[4 * (kMaxP - 2) * BST];
   const int n_rt = (a.nrhs + RT - 1) / RT;
-  int rest = blockIdx.x;
+  int rest = bid;
   const int rg = rest % a.row_groups; rest /= a.row_groups;
   const int rt = rest % n_rt; rest /= n_rt;
   const int pole = rest % a.npole;
@@ -433,17 +472,30 @@ __global__ __launch_bounds__(kBlock) void k_leaf_down_mm(MmLeafDownArgs<T> a) {
   });
 }
 
+template <class T, int NT>
+__global__ __launch_bounds__(kBlock) void k_leaf_down_mm(MmLeafDownArgs<T> a) {
+  leaf_down_body<T, NT>(a, blockIdx.x);
+}
+
+template <class T, int NT>
+__global__ __launch_bounds__(kBlock) void k_leaf_down_mm_multi(Multi<MmLeafDownArgs<T>> m) {
+  int i;
+  const int bid = m.locate(blockIdx.x, i);
+  const MmLeafDownArgs<T> a = m.args[i];
+  leaf_down_body<T, NT>(a, bid);
+}
+
 // ---- leaf downward fused with the pole sum ----------------------------------------
 // block = (leaf, rhs tile, row group); it walks the poles in order:
 //   y_m = w_m - S_m u_e,m,  u' = sum_m Re(cu_m y_m),  v' = (beta u0 + sum_m Re(cv_m y_m)) / tau,
 // so the per-pole solutions never go back to HBM.  Accumulation is FP64.
 template <class T, int NT>
-__global__ __launch_bounds__(kBlock) void k_leaf_down_sum_mm(MmLeafDownArgs<T> a) {
+__device__ __forceinline__ void leaf_down_sum_body(const MmLeafDownArgs<T>& a, const int bid) {
   using C = typename MM<T>::C;
   constexpr int RT = 16 * NT, BST = RT + 1;
   __shared__ C Bs[4 * (kMaxP - 2) * BST];
   const int n_rt = (a.nrhs + RT - 1) / RT;
-  int rest = blockIdx.x;
+  int rest = bid;
   const int rg = rest % a.row_groups; rest /= a.row_groups;
   const int rt = rest % n_rt;
   const int leaf = rest / n_rt;
@@ -512,16 +564,29 @@ __global__ __launch_bounds__(kBlock) void k_leaf_down_sum_mm(MmLeafDownArgs<T> a
     }
 }
 
+template <class T, int NT>
+__global__ __launch_bounds__(kBlock) void k_leaf_down_sum_mm(MmLeafDownArgs<T> a) {
+  leaf_down_sum_body<T, NT>(a, blockIdx.x);
+}
+
+template <class T, int NT>
+__global__ __launch_bounds__(kBlock) void k_leaf_down_sum_mm_multi(Multi<MmLeafDownArgs<T>> m) {
+  int i;
+  const int bid = m.locate(blockIdx.x, i);
+  const MmLeafDownArgs<T> a = m.args[i];
+  leaf_down_sum_body<T, NT>(a, bid);
+}
+
 // ---- shallow water: wall values at the root ------------------------------------
 //   eta_b = Q (rhs_b - a h_root),  rhs_b = (a n.v0 - f t.v0) / (c tau)
 // block = (pole, rhs tile, row group of 64 wall slots)
 template <class T, int NT>
-__global__ __launch_bounds__(kBlock) void k_sw_root_mm(SwRootArgs<T> a) {
+__device__ __forceinline__ void sw_root_body(const SwRootArgs<T>& a, const int bid) {
   using C = typename MM<T>::C;
   constexpr int RT = 16 * NT, BST = RT + 1;
   __shared__ C Bs[kKC * BST];
   const int n_rt = (a.nrhs + RT - 1) / RT;
-  int rest = blockIdx.x;
+  int rest = bid;
   const int rg = rest % a.row_groups; rest /= a.row_groups;
   const int rt = rest % n_rt;
   const int pole = rest / n_rt;
@@ -569,6 +634,19 @@ __global__ __launch_bounds__(kBlock) void k_sw_root_mm(SwRootArgs<T> a) {
     const int rhs = rt * RT + j;
     if (rhs < r) u[(long long)row * r + rhs] = c;
   });
+}
+
+template <class T, int NT>
+__global__ __launch_bounds__(kBlock) void k_sw_root_mm(SwRootArgs<T> a) {
+  sw_root_body<T, NT>(a, blockIdx.x);
+}
+
+template <class T, int NT>
+__global__ __launch_bounds__(kBlock) void k_sw_root_mm_multi(Multi<SwRootArgs<T>> m) {
+  int i;
+  const int bid = m.locate(blockIdx.x, i);
+  const SwRootArgs<T> a = m.args[i];
+  sw_root_body<T, NT>(a, bid);
 }
 
 template <class T>
@@ -653,6 +731,63 @@ hipError_t launch_leaf_down_sum_mm(const MmLeafDownArgs<T>& a, int n_leaf, int n
   else hipLaunchKernelGGL((k_leaf_down_sum_mm<T, 1>), grid, dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
+
+// ---- multi-instance launchers ------------------------------------------------------
+
+template <class T>
+size_t leaf_up_lds_bytes(int q, int nt) {
+  return nt == 2 ? leaf_up_lds<T, 2>(q) : leaf_up_lds<T, 1>(q);
+}
+
+template <class K>
+static hipError_t allow_lds(K* kernel, size_t lds) {
+  if (lds <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <class T>
+hipError_t launch_leaf_up_mm_multi(const Multi<MmLeafUpArgs<T>>& m, int blocks, int nt, size_t lds,
+                                   hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  if (nt == 2) {
+    const hipError_t e = allow_lds(&k_leaf_up_mm_multi<T, 2>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_leaf_up_mm_multi<T, 2>), dim3(blocks), dim3(kBlock), lds, s, m);
+  } else {
+    const hipError_t e = allow_lds(&k_leaf_up_mm_multi<T, 1>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_leaf_up_mm_multi<T, 1>), dim3(blocks), dim3(kBlock), lds, s, m);
+  }
+  return hipGetLastError();
+}
+
+#define HX_MULTI_LAUNCHER(NAME, ARGS)                                                          \
+  template <class T>                                                                           \
+  hipError_t launch_##NAME##_multi(const Multi<ARGS<T>>& m, int blocks, int nt, hipStream_t s) { \
+    if (blocks <= 0) return hipSuccess;                                                        \
+    if (nt == 2) hipLaunchKernelGGL((k_##NAME##_multi<T, 2>), dim3(blocks), dim3(kBlock), 0, s, m); \
+    else hipLaunchKernelGGL((k_##NAME##_multi<T, 1>), dim3(blocks), dim3(kBlock), 0, s, m);   \
+    return hipGetLastError();                                                                  \
+  }
+HX_MULTI_LAUNCHER(merge_up_mm, MmMergeArgs)
+HX_MULTI_LAUNCHER(merge_down_mm, MmMergeArgs)
+HX_MULTI_LAUNCHER(leaf_down_mm, MmLeafDownArgs)
+HX_MULTI_LAUNCHER(leaf_down_sum_mm, MmLeafDownArgs)
+HX_MULTI_LAUNCHER(sw_root_mm, SwRootArgs)
+#undef HX_MULTI_LAUNCHER
+
+#define HX_INST(T)                                                                                     \
+  template size_t leaf_up_lds_bytes<T>(int, int);                                                      \
+  template hipError_t launch_leaf_up_mm_multi<T>(const Multi<MmLeafUpArgs<T>>&, int, int, size_t, hipStream_t); \
+  template hipError_t launch_merge_up_mm_multi<T>(const Multi<MmMergeArgs<T>>&, int, int, hipStream_t);   \
+  template hipError_t launch_merge_down_mm_multi<T>(const Multi<MmMergeArgs<T>>&, int, int, hipStream_t); \
+  template hipError_t launch_leaf_down_mm_multi<T>(const Multi<MmLeafDownArgs<T>>&, int, int, hipStream_t); \
+  template hipError_t launch_leaf_down_sum_mm_multi<T>(const Multi<MmLeafDownArgs<T>>&, int, int, hipStream_t); \
+  template hipError_t launch_sw_root_mm_multi<T>(const Multi<SwRootArgs<T>>&, int, int, hipStream_t);
+HX_INST(float)
+HX_INST(double)
+#undef HX_INST
 
 template hipError_t launch_leaf_down_sum_mm<double>(const MmLeafDownArgs<double>&, int, int, hipStream_t);
 template hipError_t launch_leaf_down_sum_mm<float>(const MmLeafDownArgs<float>&, int, int, hipStream_t);

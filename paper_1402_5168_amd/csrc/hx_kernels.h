@@ -74,6 +74,28 @@ hipError_t launch_pole_sum(const PoleSumArgs& a, int n_leaf, hipStream_t s);
 
 // ---- solve stage, many right-hand sides (matrix cores) -----------------------
 
+// Several instances in one launch: instance i owns the blocks
+// [first[i], first[i+1]) and its arguments are args[i] (device tables).
+template <class A>
+struct Multi {
+  const A* args;
+  const int* first;   // n + 1 entries
+  int n;
+  __device__ int locate(int b, int& i) const {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (first[mid] <= b) lo = mid;
+      else hi = mid - 1;
+    }
+    i = lo;
+    return b - first[lo];
+  }
+};
+
+// Right-hand-side tiles of 16 * nt columns.
+inline int mm_tiles(int nrhs, int nt) { return (nrhs + 16 * nt - 1) / (16 * nt); }
+
 template <class T> struct Cplx;
 template <> struct Cplx<double> { typedef double2 type; };
 template <> struct Cplx<float> { typedef float2 type; };
@@ -189,6 +211,7 @@ struct SwPostArgs {
   double sx, sy, c, f, beta1, beta2, inv_tau;
   const double* esum;        // precision form: first-sweep sums [leaf][3][p*p][rhs] (null: none)
   int n_leaf;
+  int RR;                    // right-hand sides per block (set by sw_post_rr)
 };
 
 template <class T>
@@ -213,6 +236,12 @@ hipError_t launch_sw_wall(const SwWallArgs& a, hipStream_t s);
 hipError_t launch_sw_root_form(const SwRootFormArgs& a, int chunk, hipStream_t s);
 template <class T> hipError_t launch_sw_post(const SwPostArgs<T>& a, int n_leaf, hipStream_t s);
 template <class T> hipError_t launch_sw_root_mm(const SwRootArgs<T>& a, hipStream_t s);
+hipError_t launch_sw_prep_multi(const Multi<SwPrepArgs>& m, int blocks, hipStream_t s);
+hipError_t launch_sw_wall_multi(const Multi<SwWallArgs>& m, int blocks, hipStream_t s);
+template <class T>
+hipError_t launch_sw_post_multi(const Multi<SwPostArgs<T>>& m, int blocks, size_t lds, hipStream_t s);
+int sw_post_rr(int p, int nrhs);
+size_t sw_post_lds_bytes(int p, int RR);
 
 // FP64 residual of the collocation equations for the precision form.
 struct ResidualArgs {
@@ -242,8 +271,25 @@ struct ResidualArgs {
   double f, inv_c;
   const SwCoef* swc;
   double* esum;              // first-sweep pole sums E0, E1, E2 [leaf][3][p*p][rhs]
+  int RR;                    // right-hand sides per block (set by residual_rr)
 };
 hipError_t launch_residual(const ResidualArgs& a, int n_leaf, hipStream_t s);
+int residual_rr(const ResidualArgs& a);                       // RR for one instance
+size_t residual_lds_bytes(int p, int RR, int nsrc);
+hipError_t launch_residual_multi(const Multi<ResidualArgs>& m, int blocks, bool sw, size_t lds,
+                                 hipStream_t s);
+
+// Multi-instance variants: one launch over the blocks of every instance in
+// the table, all with the same tile count nt (1 or 2) and LDS bytes.
+template <class T> hipError_t launch_leaf_up_mm_multi(const Multi<MmLeafUpArgs<T>>& m, int blocks, int nt, size_t lds, hipStream_t s);
+template <class T> hipError_t launch_merge_up_mm_multi(const Multi<MmMergeArgs<T>>& m, int blocks, int nt, hipStream_t s);
+template <class T> hipError_t launch_merge_down_mm_multi(const Multi<MmMergeArgs<T>>& m, int blocks, int nt, hipStream_t s);
+template <class T> hipError_t launch_leaf_down_mm_multi(const Multi<MmLeafDownArgs<T>>& m, int blocks, int nt, hipStream_t s);
+template <class T> hipError_t launch_leaf_down_sum_mm_multi(const Multi<MmLeafDownArgs<T>>& m, int blocks, int nt, hipStream_t s);
+template <class T> hipError_t launch_sw_root_mm_multi(const Multi<SwRootArgs<T>>& m, int blocks, int nt, hipStream_t s);
+// LDS bytes of the leaf upward kernel (above 64 KiB the launcher raises the
+// kernel's dynamic LDS limit).
+template <class T> size_t leaf_up_lds_bytes(int q, int nt);
 
 // nt = right-hand-side tiles of 16 per block (1 or 2)
 template <class T> hipError_t launch_leaf_up_mm(const MmLeafUpArgs<T>& a, int n_leaf, int nt, hipStream_t s);

@@ -62,6 +62,8 @@ hx_status fail(hx_status st, const char* fmt, ...) {
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+constexpr size_t kArgsMax = 256;   // bytes of the largest argument block
+constexpr size_t kTabSlot = 512;   // table bytes reserved per recorded stage
 bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
 // Chebyshev-Lobatto differentiation matrix on ascending nodes
@@ -107,6 +109,7 @@ struct Instance {
   long long pole_stride = 0;                // complex elements per pole block
   long long leaf_ops = 0, merge_ops = 0;    // complex elements per pole
   double max_abs_R = 0.0, fit_X = 0.0, sum_abs_b = 0.0;
+  int tune_nt[8] = {0, 0, 0, 0, 0, 0, 0, 0}; // per stage: right-hand-side tiles (0: default)
   bool fp32 = false;                        // precision form: FP32 operators and sweeps
   // shallow water: wall nodes are exterior unknowns up to the root
   bool sw = false;
@@ -128,6 +131,14 @@ struct Instance {
   size_t cbytes() const { return fp32 ? sizeof(float2) : sizeof(double2); }
 };
 
+// One fused launch of the batched instances: a stage kind and tile count,
+// its instances' argument table and block offsets inside the arena.
+struct Group {
+  int kind, nt, cls, n;
+  long long blocks;
+  size_t lds, args_off, first_off;
+};
+
 }  // namespace
 
 struct hx_plan {
@@ -145,6 +156,12 @@ struct hx_plan {
   hipStream_t graph_stream = nullptr;
   int* d_flag = nullptr;  // inside the arena
   size_t d_flag_off = 0;
+  // stage tables of the batched instances (fused launches)
+  size_t d_tab = 0, tab_bytes = 0;
+  bool tab_ready = false;
+  std::vector<double*> tab_states;
+  std::vector<Group> groups;
+  std::vector<unsigned char> tab_blob;
 };
 
 namespace {
@@ -378,6 +395,15 @@ void build_tree(Instance& I) {
   I.pole_stride = align_up((size_t)op, 16);
 }
 
+// Stages an instance records per step on the matrix-core path.
+size_t stage_count(const Instance& I) {
+  const size_t nl = I.levels.size(), passes = I.fp32 ? 2 : 1;
+  size_t n = passes * (1 + 2 * (nl - 1) + 1 + (I.sw ? 1 : 0));
+  if (I.fp32) n += 1;                 // residual
+  if (I.sw) n += 3;                   // sources, wall values, velocity recovery
+  return n;
+}
+
 void layout_arena(hx_plan* plan) {
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -386,6 +412,11 @@ void layout_arena(hx_plan* plan) {
     return o;
   };
   plan->d_flag_off = take(sizeof(int));
+  size_t n_stages = 0;
+  for (auto& I : plan->inst)
+    if (I.fp32 || I.sw || I.nrhs > 1) n_stages += stage_count(I);
+  plan->tab_bytes = n_stages * kTabSlot + kAlign;
+  plan->d_tab = take(plan->tab_bytes);
   for (auto& I : plan->inst) {
     const size_t cb = I.cbytes();
     I.d_ops = take(cb * (size_t)I.pole_stride * I.npole);
@@ -1113,153 +1144,116 @@ struct Prof {
   } while (0)
 
 
-hx_status enqueue_batched(hx_plan* plan, const Instance& I, double* state, hipStream_t s, Prof* prof) {
-  char* a = plan->arena;
-  const double2* ops = reinterpret_cast<const double2*>(a + I.d_ops);
-  double2* w = reinterpret_cast<double2*>(a + I.d_w);
-  const auto* leaves = reinterpret_cast<const LeafDesc*>(a + I.d_leaves);
-  const auto* coef = reinterpret_cast<const PoleCoef*>(a + I.d_coef);
-  const int* idx = reinterpret_cast<const int*>(a + I.d_idx);
-  const long long n_int = (long long)I.n_leaf * I.q2;
-  auto vec = [&](size_t off) { return reinterpret_cast<double2*>(a + off); };
-  const int nt = I.nrhs > 16 ? 2 : 1;
+// ---- batched instances: recorded stages, fused over instances ---------------------
+//
+// Every instance that runs on the matrix cores records its step as a list of
+// stages (kernel kind, tile count, block count, LDS bytes and its argument
+// block).  The stages of all instances are then ordered by (pass, stage,
+// level) and stages of the same kind and tile count become ONE launch over
+// the blocks of every instance in it, its arguments read from a table in the
+// arena.  Levels are counted from the elements up, so an instance with fewer
+// levels simply takes part in fewer merge launches; its own order (upward
+// levels ascending, downward descending) is kept.
 
-  hx::MmLeafUpArgs<double> lu{};
-  lu.ops = ops;
-  lu.pole_stride = I.pole_stride;
-  lu.leaves = leaves;
-  lu.npole = I.npole;
-  lu.nrhs = I.nrhs;
-  lu.q = I.q;
-  lu.state = state;
-  lu.rhs_stride = 2 * n_int;
-  lu.n_int = (int)n_int;
-  lu.nsrc = 2;
-  lu.coef = coef;
-  lu.inv_tau = 1.0 / I.tau;
-  lu.inv_tau2 = 1.0 / (I.tau * I.tau);
-  lu.nrow = reinterpret_cast<const double*>(a + I.d_nrow);
-  lu.sx = 2.0 * I.mesh.nex / (I.mesh.x1 - I.mesh.x0);
-  lu.sy = 2.0 * I.mesh.ney / (I.mesh.y1 - I.mesh.y0);
-  lu.w = w;
-  lu.w_pole = n_int;
-  lu.h = vec(I.levels[0].d_h);
-  lu.h_pole = I.levels[0].total_ext;
-  TIMED(HX_K_LEAF_UP, hx::launch_leaf_up_mm<double>(lu, I.n_leaf, nt, s));
+enum StageKind : int {
+  K_LU_D, K_LU_F, K_MU_D, K_MU_F, K_MD_D, K_MD_F, K_LD_D, K_LD_F, K_LDS_D, K_LDS_F,
+  K_ROOT_D, K_ROOT_F, K_RES_W, K_RES_S, K_PREP, K_WALL, K_POST_D, K_POST_F
+};
+enum StageOrder : int { O_PREP, O_LEAF_UP, O_MERGE_UP, O_ROOT, O_MERGE_DOWN, O_LEAF_DOWN, O_RESIDUAL, O_POST };
 
-  const size_t nl = I.levels.size();
-  for (size_t l = 1; l < nl; ++l) {
-    const Level& L = I.levels[l];
-    hx::MmMergeArgs<double> m{};
-    m.ops = ops;
-    m.pole_stride = I.pole_stride;
-    m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
-    m.idx = idx;
-    m.npole = I.npole;
-    m.nrhs = I.nrhs;
-    m.row_groups = std::max(1, (L.max_ext + 63) / 64);
-    m.child = vec(I.levels[l - 1].d_h);
-    m.child_pole = I.levels[l - 1].total_ext;
-    m.self = vec(L.d_h);
-    m.self_pole = L.total_ext;
-    m.g3 = vec(L.d_g3);
-    m.g3_pole = L.total_n3;
-    TIMED(HX_K_MERGE_UP, hx::launch_merge_up_mm<double>(m, (int)L.boxes.size(), nt, s));
+
+struct Rec {
+  int pass, order, level, kind, nt, cls, inst;
+  long long blocks;
+  size_t lds, args_size;
+  unsigned char args[kArgsMax];
+};
+
+struct Recorder {
+  std::vector<Rec> recs;
+  template <class A>
+  void add(int pass, int order, int level, int kind, int nt, long long blocks, size_t lds,
+           const A& a, int cls, int inst) {
+    static_assert(sizeof(A) <= kArgsMax, "argument block too large");
+    Rec r;
+    r.pass = pass;
+    r.order = order;
+    r.level = level;
+    r.kind = kind;
+    r.nt = nt;
+    r.cls = cls;
+    r.inst = inst;
+    r.blocks = blocks;
+    r.lds = lds;
+    r.args_size = sizeof(A);
+    std::memcpy(r.args, &a, sizeof(A));
+    recs.push_back(r);
   }
-  for (size_t l = nl - 1; l >= 1; --l) {
-    const Level& L = I.levels[l];
-    hx::MmMergeArgs<double> m{};
-    m.ops = ops;
-    m.pole_stride = I.pole_stride;
-    m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
-    m.idx = idx;
-    m.npole = I.npole;
-    m.nrhs = I.nrhs;
-    m.row_groups = std::max(1, (L.max_n3 + 63) / 64);
-    m.child = vec(I.levels[l - 1].d_u);
-    m.child_pole = I.levels[l - 1].total_ext;
-    m.self = vec(L.d_u);
-    m.self_pole = L.total_ext;
-    m.g3 = vec(L.d_g3);
-    m.g3_pole = L.total_n3;
-    TIMED(HX_K_MERGE_DOWN, hx::launch_merge_down_mm<double>(m, (int)L.boxes.size(), nt, s));
-  }
-  hx::MmLeafDownArgs<double> ld{};
-  ld.ops = ops;
-  ld.pole_stride = I.pole_stride;
-  ld.leaves = leaves;
-  ld.npole = I.npole;
-  ld.nrhs = I.nrhs;
-  ld.q = I.q;
-  ld.row_groups = (I.q2 + 63) / 64;
-  ld.u = vec(I.levels[0].d_u);
-  ld.u_pole = I.levels[0].total_ext;
-  ld.w = w;
-  ld.w_pole = n_int;
-  ld.coef = coef;
-  ld.state = state;
-  ld.rhs_stride = 2 * n_int;
-  ld.n_int = (int)n_int;
-  ld.beta = I.beta;
-  ld.inv_tau = 1.0 / I.tau;
-  TIMED(HX_K_LEAF_DOWN, hx::launch_leaf_down_sum_mm<double>(ld, I.n_leaf, nt, s));
-  return HX_OK;
+};
+
+// Right-hand-side tile count of a stage: the tuned choice, else two tiles of
+// 16 when there are more than 16 right-hand sides.
+int stage_nt(const Instance& I, int order) {
+  const int t = I.tune_nt[order];
+  if (t == 1 || (t == 2 && I.nrhs > 16)) return t;
+  return I.nrhs > 16 ? 2 : 1;
 }
 
-// Shallow water: sources (eta, div v, curl v) and wall values of the state,
-// the upward sweep to the root, the root's oblique wall system, the
-// downward sweep, then the pole sums and the velocity recovery.  In the
-// precision form (T = float) the sweep runs twice: the FP64 residual of the
-// first (interior rows, flux jumps and wall rows) drives the second, and
-// the first sweep's pole sums, kept in FP64, are added to the second's.
 template <class T>
-hx_status enqueue_sw(hx_plan* plan, const Instance& I, double* state, hipStream_t s, Prof* prof) {
+void record_instance(const hx_plan* plan, const Instance& I, int inst, double* state, Recorder& R) {
   using C = typename hx::Cplx<T>::type;
   constexpr bool refine = sizeof(T) == sizeof(float);
+  constexpr bool dbl = !refine;
   char* a = plan->arena;
   const C* ops = reinterpret_cast<const C*>(a + I.d_ops);
   C* w = reinterpret_cast<C*>(a + I.d_w);
-  double* prep = reinterpret_cast<double*>(a + I.d_prep);
-  double* wallv = reinterpret_cast<double*>(a + I.d_wallv);
   const auto* leaves = reinterpret_cast<const LeafDesc*>(a + I.d_leaves);
   const auto* coef = reinterpret_cast<const PoleCoef*>(a + I.d_coef);
-  const auto* swc = reinterpret_cast<const SwCoef*>(a + I.d_swc);
-  const auto* wall = reinterpret_cast<const int4*>(a + I.d_wall);
   const int* idx = reinterpret_cast<const int*>(a + I.d_idx);
-  double2* dn = refine ? reinterpret_cast<double2*>(a + I.d_dn) : nullptr;
-  C* gres = refine ? reinterpret_cast<C*>(a + I.d_gres) : nullptr;
-  double* esum = refine ? reinterpret_cast<double*>(a + I.d_esum) : nullptr;
-  const long long n_int = (long long)I.n_leaf * I.q2;
   auto vec = [&](size_t off) { return reinterpret_cast<C*>(a + off); };
   auto dptr = [&](size_t off) { return reinterpret_cast<const double*>(a + off); };
-  const int nt = I.nrhs > 16 ? 2 : 1;
+  const bool sw = I.sw;
+  const long long n_int = (long long)I.n_leaf * I.q2;
+  const long long stride = (long long)I.nfield * n_int;
   const double sx = 2.0 * I.mesh.nex / (I.mesh.x1 - I.mesh.x0);
   const double sy = 2.0 * I.mesh.ney / (I.mesh.y1 - I.mesh.y0);
+  double* prep = sw ? reinterpret_cast<double*>(a + I.d_prep) : nullptr;
+  double* wallv = sw ? reinterpret_cast<double*>(a + I.d_wallv) : nullptr;
+  const auto* wall = sw ? reinterpret_cast<const int4*>(a + I.d_wall) : nullptr;
+  const auto* swc = sw ? reinterpret_cast<const SwCoef*>(a + I.d_swc) : nullptr;
+  double2* dn = refine ? reinterpret_cast<double2*>(a + I.d_dn) : nullptr;
+  C* gres = refine ? reinterpret_cast<C*>(a + I.d_gres) : nullptr;
+  C* y0 = refine ? reinterpret_cast<C*>(a + I.d_y0) : nullptr;
+  double* esum = (refine && sw) ? reinterpret_cast<double*>(a + I.d_esum) : nullptr;
+  const double* src = sw ? prep : state;
+  const size_t nl = I.levels.size();
 
-  hx::SwPrepArgs pa{};
-  pa.state = state;
-  pa.prep = prep;
-  pa.rhs_stride = 3 * n_int;
-  pa.n_int = (int)n_int;
-  pa.nrhs = I.nrhs;
-  pa.q = I.q;
-  pa.Dq = dptr(I.d_Dq);
-  pa.sx = sx;
-  pa.sy = sy;
-  TIMED(HX_K_SW_PREP, hx::launch_sw_prep(pa, I.n_leaf, s));
-  hx::SwWallArgs wa{};
-  wa.state = state;
-  wa.rhs_stride = 3 * n_int;
-  wa.n_int = (int)n_int;
-  wa.nrhs = I.nrhs;
-  wa.q = I.q;
-  wa.n_wall = I.n_wall;
-  wa.wall = wall;
-  wa.w_lo = dptr(I.d_wlo);
-  wa.w_hi = dptr(I.d_whi);
-  wa.out = wallv;
-  TIMED(HX_K_SW_PREP, hx::launch_sw_wall(wa, s));
-
+  if (sw) {
+    hx::SwPrepArgs pa{};
+    pa.state = state;
+    pa.prep = prep;
+    pa.rhs_stride = stride;
+    pa.n_int = (int)n_int;
+    pa.nrhs = I.nrhs;
+    pa.q = I.q;
+    pa.Dq = dptr(I.d_Dq);
+    pa.sx = sx;
+    pa.sy = sy;
+    R.add(0, O_PREP, 0, K_PREP, 1, (long long)I.n_leaf * I.nrhs, 0, pa, HX_K_SW_PREP, inst);
+    hx::SwWallArgs wa{};
+    wa.state = state;
+    wa.rhs_stride = stride;
+    wa.n_int = (int)n_int;
+    wa.nrhs = I.nrhs;
+    wa.q = I.q;
+    wa.n_wall = I.n_wall;
+    wa.wall = wall;
+    wa.w_lo = dptr(I.d_wlo);
+    wa.w_hi = dptr(I.d_whi);
+    wa.out = wallv;
+    R.add(0, O_PREP, 1, K_WALL, 1, ((long long)I.n_wall * I.nrhs + hx::kBlock - 1) / hx::kBlock, 0,
+          wa, HX_K_SW_PREP, inst);
+  }
   const int passes = refine ? 2 : 1;
   for (int pass = 0; pass < passes; ++pass) {
     hx::MmLeafUpArgs<T> lu{};
@@ -1269,10 +1263,10 @@ hx_status enqueue_sw(hx_plan* plan, const Instance& I, double* state, hipStream_
     lu.npole = I.npole;
     lu.nrhs = I.nrhs;
     lu.q = I.q;
-    lu.state = prep;
-    lu.rhs_stride = 3 * n_int;
+    lu.state = src;
+    lu.rhs_stride = sw ? 3 * n_int : stride;
     lu.n_int = (int)n_int;
-    lu.nsrc = 3;
+    lu.nsrc = sw ? 3 : 2;
     lu.coef = coef;
     lu.inv_tau = 1.0 / I.tau;
     lu.inv_tau2 = 1.0 / (I.tau * I.tau);
@@ -1284,9 +1278,13 @@ hx_status enqueue_sw(hx_plan* plan, const Instance& I, double* state, hipStream_
     lu.h = vec(I.levels[0].d_h);
     lu.h_pole = I.levels[0].total_ext;
     lu.gin = pass ? gres : nullptr;
-    TIMED(HX_K_LEAF_UP, hx::launch_leaf_up_mm<T>(lu, I.n_leaf, nt, s));
+    // two tiles only while the staged right-hand sides fit in 64 KiB of LDS
+    int nt = stage_nt(I, O_LEAF_UP);
+    if (nt == 2 && hx::leaf_up_lds_bytes<T>(I.q, 2) > 65536) nt = 1;
+    const size_t lds = hx::leaf_up_lds_bytes<T>(I.q, nt);
+    R.add(pass, O_LEAF_UP, 0, dbl ? K_LU_D : K_LU_F, nt,
+          (long long)I.n_leaf * I.npole * hx::mm_tiles(I.nrhs, nt), lds, lu, HX_K_LEAF_UP, inst);
 
-    const size_t nl = I.levels.size();
     for (size_t l = 1; l < nl; ++l) {
       const Level& L = I.levels[l];
       hx::MmMergeArgs<T> m{};
@@ -1305,28 +1303,35 @@ hx_status enqueue_sw(hx_plan* plan, const Instance& I, double* state, hipStream_
       m.g3_pole = L.total_n3;
       m.dn = pass ? dn : nullptr;
       m.dn_pole = I.levels[0].total_ext;
-      TIMED(HX_K_MERGE_UP, hx::launch_merge_up_mm<T>(m, (int)L.boxes.size(), nt, s));
+      const int mnt = stage_nt(I, O_MERGE_UP);
+      R.add(pass, O_MERGE_UP, (int)l, dbl ? K_MU_D : K_MU_F, mnt,
+            (long long)L.boxes.size() * I.npole * hx::mm_tiles(I.nrhs, mnt) * m.row_groups, 0, m,
+            HX_K_MERGE_UP, inst);
     }
-    const Level& R = I.levels[nl - 1];
-    hx::SwRootArgs<T> ra{};
-    ra.ops = ops;
-    ra.pole_stride = I.pole_stride;
-    ra.q_off = I.q_off;
-    ra.n = I.n_wall;
-    ra.npole = I.npole;
-    ra.nrhs = I.nrhs;
-    ra.row_groups = (I.n_wall + 63) / 64;
-    ra.coef = coef;
-    ra.inv_tau = 1.0 / I.tau;
-    ra.inv_c = 1.0 / I.cw;
-    ra.f = I.f;
-    ra.wall = wallv;
-    ra.h = vec(R.d_h);
-    ra.u = vec(R.d_u);
-    ra.rw = pass ? dn : nullptr;
-    ra.rw_pole = I.levels[0].total_ext;
-    ra.wall_info = wall;
-    TIMED(HX_K_SW_ROOT, hx::launch_sw_root_mm<T>(ra, s));
+    if (sw) {
+      const Level& Rt = I.levels[nl - 1];
+      hx::SwRootArgs<T> ra{};
+      ra.ops = ops;
+      ra.pole_stride = I.pole_stride;
+      ra.q_off = I.q_off;
+      ra.n = I.n_wall;
+      ra.npole = I.npole;
+      ra.nrhs = I.nrhs;
+      ra.row_groups = (I.n_wall + 63) / 64;
+      ra.coef = coef;
+      ra.inv_tau = 1.0 / I.tau;
+      ra.inv_c = 1.0 / I.cw;
+      ra.f = I.f;
+      ra.wall = wallv;
+      ra.h = vec(Rt.d_h);
+      ra.u = vec(Rt.d_u);
+      ra.rw = pass ? dn : nullptr;
+      ra.rw_pole = I.levels[0].total_ext;
+      ra.wall_info = wall;
+      const int rnt = stage_nt(I, O_ROOT);
+      R.add(pass, O_ROOT, 0, dbl ? K_ROOT_D : K_ROOT_F, rnt,
+            (long long)I.npole * hx::mm_tiles(I.nrhs, rnt) * ra.row_groups, 0, ra, HX_K_SW_ROOT, inst);
+    }
     for (size_t l = nl - 1; l >= 1; --l) {
       const Level& L = I.levels[l];
       hx::MmMergeArgs<T> m{};
@@ -1343,170 +1348,12 @@ hx_status enqueue_sw(hx_plan* plan, const Instance& I, double* state, hipStream_
       m.self_pole = L.total_ext;
       m.g3 = vec(L.d_g3);
       m.g3_pole = L.total_n3;
-      TIMED(HX_K_MERGE_DOWN, hx::launch_merge_down_mm<T>(m, (int)L.boxes.size(), nt, s));
+      const int mnt = stage_nt(I, O_MERGE_DOWN);
+      R.add(pass, O_MERGE_DOWN, -(int)l, dbl ? K_MD_D : K_MD_F, mnt,
+            (long long)L.boxes.size() * I.npole * hx::mm_tiles(I.nrhs, mnt) * m.row_groups, 0, m,
+            HX_K_MERGE_DOWN, inst);
     }
-    // element interiors y = w - S u_e: over w, or into y0 (first sweep of
-    // the precision form)
     hx::MmLeafDownArgs<T> ld{};
-    ld.ops = ops;
-    ld.pole_stride = I.pole_stride;
-    ld.leaves = leaves;
-    ld.npole = I.npole;
-    ld.nrhs = I.nrhs;
-    ld.q = I.q;
-    ld.row_groups = (I.q2 + 63) / 64;
-    ld.u = vec(I.levels[0].d_u);
-    ld.u_pole = I.levels[0].total_ext;
-    ld.w = w;
-    ld.w_pole = n_int;
-    ld.y0 = (refine && pass == 0) ? vec(I.d_y0) : w;
-    TIMED(HX_K_LEAF_DOWN, hx::launch_leaf_down_mm<T>(ld, I.n_leaf, nt, s));
-    if (refine && pass == 0) {
-      hx::ResidualArgs rs{};
-      rs.leaves = leaves;
-      rs.npole = I.npole;
-      rs.nrhs = I.nrhs;
-      rs.p = I.mesh.p;
-      rs.q = I.q;
-      rs.c2 = dptr(I.d_c2);
-      rs.D = dptr(I.d_D);
-      rs.sx = sx;
-      rs.sy = sy;
-      rs.tau = I.tau;
-      rs.coef = coef;
-      rs.state = prep;
-      rs.rhs_stride = 3 * n_int;
-      rs.n_int = (int)n_int;
-      rs.y0 = reinterpret_cast<const float2*>(a + I.d_y0);
-      rs.w_pole = n_int;
-      rs.ue = reinterpret_cast<const float2*>(a + I.levels[0].d_u);
-      rs.e_pole = I.levels[0].total_ext;
-      rs.gres = reinterpret_cast<float2*>(gres);
-      rs.dn = dn;
-      rs.nsrc = 3;
-      rs.n_leaf = I.n_leaf;
-      rs.slot_wall = reinterpret_cast<const int*>(a + I.d_slotw);
-      rs.wallv = wallv;
-      rs.n_wall = I.n_wall;
-      rs.Dq = dptr(I.d_Dq);
-      rs.f = I.f;
-      rs.inv_c = 1.0 / I.cw;
-      rs.swc = swc;
-      rs.esum = esum;
-      TIMED(HX_K_RESIDUAL, hx::launch_residual(rs, I.n_leaf, s));
-    }
-  }
-  hx::SwPostArgs<T> po{};
-  po.leaves = leaves;
-  po.npole = I.npole;
-  po.nrhs = I.nrhs;
-  po.p = I.mesh.p;
-  po.q = I.q;
-  po.D = dptr(I.d_D);
-  po.coef = swc;
-  po.y = w;
-  po.y_pole = n_int;
-  po.ue = vec(I.levels[0].d_u);
-  po.e_pole = I.levels[0].total_ext;
-  po.state = state;
-  po.rhs_stride = 3 * n_int;
-  po.n_int = (int)n_int;
-  po.sx = sx;
-  po.sy = sy;
-  po.c = I.cw;
-  po.f = I.f;
-  po.beta1 = I.beta1;
-  po.beta2 = I.beta2;
-  po.inv_tau = 1.0 / I.tau;
-  po.esum = esum;
-  po.n_leaf = I.n_leaf;
-  TIMED(HX_K_POLE_SUM, hx::launch_sw_post<T>(po, I.n_leaf, s));
-  return HX_OK;
-}
-
-// Precision form: FP32 sweep, FP64 residual, FP32 correction sweep, FP64
-// pole sum of the corrected solutions.
-hx_status enqueue_refine(hx_plan* plan, const Instance& I, double* state, hipStream_t s, Prof* prof) {
-  char* a = plan->arena;
-  const float2* ops = reinterpret_cast<const float2*>(a + I.d_ops);
-  float2* w = reinterpret_cast<float2*>(a + I.d_w);
-  float2* y0 = reinterpret_cast<float2*>(a + I.d_y0);
-  float2* gres = reinterpret_cast<float2*>(a + I.d_gres);
-  double2* dn = reinterpret_cast<double2*>(a + I.d_dn);
-  const auto* leaves = reinterpret_cast<const LeafDesc*>(a + I.d_leaves);
-  const auto* coef = reinterpret_cast<const PoleCoef*>(a + I.d_coef);
-  const int* idx = reinterpret_cast<const int*>(a + I.d_idx);
-  const long long n_int = (long long)I.n_leaf * I.q2;
-  auto vec = [&](size_t off) { return reinterpret_cast<float2*>(a + off); };
-  const int nt = I.nrhs > 16 ? 2 : 1;
-  const double sx = 2.0 * I.mesh.nex / (I.mesh.x1 - I.mesh.x0);
-  const double sy = 2.0 * I.mesh.ney / (I.mesh.y1 - I.mesh.y0);
-
-  for (int pass = 0; pass < 2; ++pass) {
-    hx::MmLeafUpArgs<float> lu{};
-    lu.ops = ops;
-    lu.pole_stride = I.pole_stride;
-    lu.leaves = leaves;
-    lu.npole = I.npole;
-    lu.nrhs = I.nrhs;
-    lu.q = I.q;
-    lu.state = state;
-    lu.rhs_stride = 2 * n_int;
-    lu.n_int = (int)n_int;
-    lu.nsrc = 2;
-    lu.coef = coef;
-    lu.inv_tau = 1.0 / I.tau;
-    lu.inv_tau2 = 1.0 / (I.tau * I.tau);
-    lu.nrow = reinterpret_cast<const double*>(a + I.d_nrow);
-    lu.sx = sx;
-    lu.sy = sy;
-    lu.w = w;
-    lu.w_pole = n_int;
-    lu.h = vec(I.levels[0].d_h);
-    lu.h_pole = I.levels[0].total_ext;
-    lu.gin = pass ? gres : nullptr;
-    TIMED(HX_K_LEAF_UP, hx::launch_leaf_up_mm<float>(lu, I.n_leaf, nt, s));
-
-    const size_t nl = I.levels.size();
-    for (size_t l = 1; l < nl; ++l) {
-      const Level& L = I.levels[l];
-      hx::MmMergeArgs<float> m{};
-      m.ops = ops;
-      m.pole_stride = I.pole_stride;
-      m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
-      m.idx = idx;
-      m.npole = I.npole;
-      m.nrhs = I.nrhs;
-      m.row_groups = std::max(1, (L.max_ext + 63) / 64);
-      m.child = vec(I.levels[l - 1].d_h);
-      m.child_pole = I.levels[l - 1].total_ext;
-      m.self = vec(L.d_h);
-      m.self_pole = L.total_ext;
-      m.g3 = vec(L.d_g3);
-      m.g3_pole = L.total_n3;
-      m.dn = pass ? dn : nullptr;
-      m.dn_pole = I.levels[0].total_ext;
-      TIMED(HX_K_MERGE_UP, hx::launch_merge_up_mm<float>(m, (int)L.boxes.size(), nt, s));
-    }
-    for (size_t l = nl - 1; l >= 1; --l) {
-      const Level& L = I.levels[l];
-      hx::MmMergeArgs<float> m{};
-      m.ops = ops;
-      m.pole_stride = I.pole_stride;
-      m.boxes = reinterpret_cast<const BoxDesc*>(a + L.d_boxes);
-      m.idx = idx;
-      m.npole = I.npole;
-      m.nrhs = I.nrhs;
-      m.row_groups = std::max(1, (L.max_n3 + 63) / 64);
-      m.child = vec(I.levels[l - 1].d_u);
-      m.child_pole = I.levels[l - 1].total_ext;
-      m.self = vec(L.d_u);
-      m.self_pole = L.total_ext;
-      m.g3 = vec(L.d_g3);
-      m.g3_pole = L.total_n3;
-      TIMED(HX_K_MERGE_DOWN, hx::launch_merge_down_mm<float>(m, (int)L.boxes.size(), nt, s));
-    }
-    hx::MmLeafDownArgs<float> ld{};
     ld.ops = ops;
     ld.pole_stride = I.pole_stride;
     ld.leaves = leaves;
@@ -1520,40 +1367,205 @@ hx_status enqueue_refine(hx_plan* plan, const Instance& I, double* state, hipStr
     ld.w_pole = n_int;
     ld.coef = coef;
     ld.state = state;
-    ld.rhs_stride = 2 * n_int;
+    ld.rhs_stride = stride;
     ld.n_int = (int)n_int;
     ld.beta = I.beta;
     ld.inv_tau = 1.0 / I.tau;
-    ld.y0 = y0;
-    if (pass == 0) {
-      TIMED(HX_K_LEAF_DOWN, hx::launch_leaf_down_mm<float>(ld, I.n_leaf, nt, s));
-      hx::ResidualArgs ra{};
-      ra.leaves = leaves;
-      ra.npole = I.npole;
-      ra.nrhs = I.nrhs;
-      ra.p = I.mesh.p;
-      ra.q = I.q;
-      ra.c2 = reinterpret_cast<const double*>(a + I.d_c2);
-      ra.D = reinterpret_cast<const double*>(a + I.d_D);
-      ra.sx = sx;
-      ra.sy = sy;
-      ra.tau = I.tau;
-      ra.coef = coef;
-      ra.state = state;
-      ra.rhs_stride = 2 * n_int;
-      ra.n_int = (int)n_int;
-      ra.y0 = y0;
-      ra.w_pole = n_int;
-      ra.ue = vec(I.levels[0].d_u);
-      ra.e_pole = I.levels[0].total_ext;
-      ra.gres = gres;
-      ra.dn = dn;
-      ra.nsrc = 2;
-      TIMED(HX_K_RESIDUAL, hx::launch_residual(ra, I.n_leaf, s));
+    const int dnt = stage_nt(I, O_LEAF_DOWN);
+    const long long tiles = hx::mm_tiles(I.nrhs, dnt);
+    const bool fused_sum = !sw && pass == passes - 1;   // wave: pole sum fused into the last sweep
+    if (fused_sum) {
+      ld.y0 = refine ? y0 : nullptr;                    // precision form: y = y0 + w - S u_e
+      R.add(pass, O_LEAF_DOWN, 0, dbl ? K_LDS_D : K_LDS_F, dnt,
+            (long long)I.n_leaf * tiles * ld.row_groups, 0, ld, HX_K_LEAF_DOWN, inst);
     } else {
-      TIMED(HX_K_LEAF_DOWN, hx::launch_leaf_down_sum_mm<float>(ld, I.n_leaf, nt, s));
+      ld.y0 = (refine && pass == 0) ? y0 : w;           // first sweep of the precision form: into y0
+      R.add(pass, O_LEAF_DOWN, 0, dbl ? K_LD_D : K_LD_F, dnt,
+            (long long)I.n_leaf * I.npole * tiles * ld.row_groups, 0, ld, HX_K_LEAF_DOWN, inst);
+    }
+    if (refine && pass == 0) {
+      hx::ResidualArgs rs{};
+      rs.leaves = leaves;
+      rs.npole = I.npole;
+      rs.nrhs = I.nrhs;
+      rs.p = I.mesh.p;
+      rs.q = I.q;
+      rs.c2 = dptr(I.d_c2);
+      rs.D = dptr(I.d_D);
+      rs.sx = sx;
+      rs.sy = sy;
+      rs.tau = I.tau;
+      rs.coef = coef;
+      rs.state = src;
+      rs.rhs_stride = sw ? 3 * n_int : stride;
+      rs.n_int = (int)n_int;
+      rs.y0 = reinterpret_cast<const float2*>(y0);
+      rs.w_pole = n_int;
+      rs.ue = reinterpret_cast<const float2*>(a + I.levels[0].d_u);
+      rs.e_pole = I.levels[0].total_ext;
+      rs.gres = reinterpret_cast<float2*>(gres);
+      rs.dn = dn;
+      rs.nsrc = sw ? 3 : 2;
+      if (sw) {
+        rs.n_leaf = I.n_leaf;
+        rs.slot_wall = reinterpret_cast<const int*>(a + I.d_slotw);
+        rs.wallv = wallv;
+        rs.n_wall = I.n_wall;
+        rs.Dq = dptr(I.d_Dq);
+        rs.f = I.f;
+        rs.inv_c = 1.0 / I.cw;
+        rs.swc = swc;
+        rs.esum = esum;
+      }
+      rs.RR = hx::residual_rr(rs);
+      R.add(pass, O_RESIDUAL, 0, sw ? K_RES_S : K_RES_W, 1,
+            (long long)I.n_leaf * ((I.nrhs + rs.RR - 1) / rs.RR),
+            hx::residual_lds_bytes(rs.p, rs.RR, rs.nsrc), rs, HX_K_RESIDUAL, inst);
     }
   }
+  if (sw) {
+    hx::SwPostArgs<T> po{};
+    po.leaves = leaves;
+    po.npole = I.npole;
+    po.nrhs = I.nrhs;
+    po.p = I.mesh.p;
+    po.q = I.q;
+    po.D = dptr(I.d_D);
+    po.coef = swc;
+    po.y = w;
+    po.y_pole = n_int;
+    po.ue = vec(I.levels[0].d_u);
+    po.e_pole = I.levels[0].total_ext;
+    po.state = state;
+    po.rhs_stride = stride;
+    po.n_int = (int)n_int;
+    po.sx = sx;
+    po.sy = sy;
+    po.c = I.cw;
+    po.f = I.f;
+    po.beta1 = I.beta1;
+    po.beta2 = I.beta2;
+    po.inv_tau = 1.0 / I.tau;
+    po.esum = esum;
+    po.n_leaf = I.n_leaf;
+    po.RR = hx::sw_post_rr(po.p, po.nrhs);
+    R.add(passes - 1, O_POST, 0, dbl ? K_POST_D : K_POST_F, 1,
+          (long long)I.n_leaf * ((I.nrhs + po.RR - 1) / po.RR), hx::sw_post_lds_bytes(po.p, po.RR),
+          po, HX_K_POLE_SUM, inst);
+  }
+}
+
+// Record every batched instance (states may be null for a count).
+void record_all(const hx_plan* plan, double* const* states, Recorder& R) {
+  for (size_t k = 0; k < plan->inst.size(); ++k) {
+    const Instance& I = plan->inst[k];
+    if (!batched(plan, I)) continue;
+    double* st = states ? states[k] : nullptr;
+    if (I.fp32) record_instance<float>(plan, I, (int)k, st, R);
+    else record_instance<double>(plan, I, (int)k, st, R);
+  }
+}
+
+// Order the stages, form the groups and pack their tables (argument
+// blocks, then n + 1 block offsets) at 256-byte aligned offsets.
+void group_stages(Recorder& R, std::vector<Group>& groups, std::vector<unsigned char>& blob) {
+  std::stable_sort(R.recs.begin(), R.recs.end(), [](const Rec& x, const Rec& y) {
+    if (x.pass != y.pass) return x.pass < y.pass;
+    if (x.order != y.order) return x.order < y.order;
+    if (x.level != y.level) return x.level < y.level;
+    if (x.kind != y.kind) return x.kind < y.kind;
+    return x.nt < y.nt;
+  });
+  groups.clear();
+  blob.clear();
+  size_t i = 0;
+  while (i < R.recs.size()) {
+    size_t j = i;
+    const Rec& h = R.recs[i];
+    while (j < R.recs.size() && R.recs[j].pass == h.pass && R.recs[j].order == h.order &&
+           R.recs[j].level == h.level && R.recs[j].kind == h.kind && R.recs[j].nt == h.nt)
+      ++j;
+    Group g{};
+    g.kind = h.kind;
+    g.nt = h.nt;
+    g.cls = h.cls;
+    g.n = (int)(j - i);
+    g.args_off = align_up(blob.size());
+    blob.resize(g.args_off + h.args_size * g.n);
+    std::vector<int> first(g.n + 1, 0);
+    long long b = 0;
+    for (size_t k = i; k < j; ++k) {
+      std::memcpy(blob.data() + g.args_off + (k - i) * h.args_size, R.recs[k].args, h.args_size);
+      first[k - i] = (int)b;
+      b += R.recs[k].blocks;
+      g.lds = std::max(g.lds, R.recs[k].lds);
+    }
+    first[g.n] = (int)b;
+    g.blocks = b;
+    g.first_off = align_up(blob.size());
+    blob.resize(g.first_off + sizeof(int) * first.size());
+    std::memcpy(blob.data() + g.first_off, first.data(), sizeof(int) * first.size());
+    groups.push_back(g);
+    i = j;
+  }
+  blob.resize(align_up(blob.size()));
+}
+
+template <class A>
+hx::Multi<A> multi_of(const hx_plan* plan, const Group& g) {
+  hx::Multi<A> m;
+  m.args = reinterpret_cast<const A*>(plan->arena + plan->d_tab + g.args_off);
+  m.first = reinterpret_cast<const int*>(plan->arena + plan->d_tab + g.first_off);
+  m.n = g.n;
+  return m;
+}
+
+hipError_t launch_group(const hx_plan* plan, const Group& g, hipStream_t s) {
+  const int b = (int)g.blocks;
+  switch (g.kind) {
+    case K_LU_D: return hx::launch_leaf_up_mm_multi<double>(multi_of<hx::MmLeafUpArgs<double>>(plan, g), b, g.nt, g.lds, s);
+    case K_LU_F: return hx::launch_leaf_up_mm_multi<float>(multi_of<hx::MmLeafUpArgs<float>>(plan, g), b, g.nt, g.lds, s);
+    case K_MU_D: return hx::launch_merge_up_mm_multi<double>(multi_of<hx::MmMergeArgs<double>>(plan, g), b, g.nt, s);
+    case K_MU_F: return hx::launch_merge_up_mm_multi<float>(multi_of<hx::MmMergeArgs<float>>(plan, g), b, g.nt, s);
+    case K_MD_D: return hx::launch_merge_down_mm_multi<double>(multi_of<hx::MmMergeArgs<double>>(plan, g), b, g.nt, s);
+    case K_MD_F: return hx::launch_merge_down_mm_multi<float>(multi_of<hx::MmMergeArgs<float>>(plan, g), b, g.nt, s);
+    case K_LD_D: return hx::launch_leaf_down_mm_multi<double>(multi_of<hx::MmLeafDownArgs<double>>(plan, g), b, g.nt, s);
+    case K_LD_F: return hx::launch_leaf_down_mm_multi<float>(multi_of<hx::MmLeafDownArgs<float>>(plan, g), b, g.nt, s);
+    case K_LDS_D: return hx::launch_leaf_down_sum_mm_multi<double>(multi_of<hx::MmLeafDownArgs<double>>(plan, g), b, g.nt, s);
+    case K_LDS_F: return hx::launch_leaf_down_sum_mm_multi<float>(multi_of<hx::MmLeafDownArgs<float>>(plan, g), b, g.nt, s);
+    case K_ROOT_D: return hx::launch_sw_root_mm_multi<double>(multi_of<hx::SwRootArgs<double>>(plan, g), b, g.nt, s);
+    case K_ROOT_F: return hx::launch_sw_root_mm_multi<float>(multi_of<hx::SwRootArgs<float>>(plan, g), b, g.nt, s);
+    case K_RES_W: return hx::launch_residual_multi(multi_of<hx::ResidualArgs>(plan, g), b, false, g.lds, s);
+    case K_RES_S: return hx::launch_residual_multi(multi_of<hx::ResidualArgs>(plan, g), b, true, g.lds, s);
+    case K_PREP: return hx::launch_sw_prep_multi(multi_of<hx::SwPrepArgs>(plan, g), b, s);
+    case K_WALL: return hx::launch_sw_wall_multi(multi_of<hx::SwWallArgs>(plan, g), b, s);
+    case K_POST_D: return hx::launch_sw_post_multi<double>(multi_of<hx::SwPostArgs<double>>(plan, g), b, g.lds, s);
+    case K_POST_F: return hx::launch_sw_post_multi<float>(multi_of<hx::SwPostArgs<float>>(plan, g), b, g.lds, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Record the batched instances for these states, group their stages and
+// upload the tables (stream-ordered, then waited for: never inside a
+// capture).  Skipped when the tables already match the states.
+hx_status prepare_tables(hx_plan* plan, double* const* states, hipStream_t s) {
+  std::vector<double*> key(states, states + plan->inst.size());
+  if (plan->tab_ready && key == plan->tab_states) return HX_OK;
+  Recorder R;
+  record_all(plan, states, R);
+  group_stages(R, plan->groups, plan->tab_blob);
+  if (plan->tab_blob.size() > plan->tab_bytes)
+    return fail(HX_ENOMEM, "stage tables of %zu bytes exceed the %zu reserved", plan->tab_blob.size(),
+                plan->tab_bytes);
+  for (const Group& g : plan->groups)
+    if (g.blocks > 0x7fffffffLL) return fail(HX_EINVAL, "a fused launch exceeds 2^31 blocks");
+  if (!plan->tab_blob.empty()) {
+    HIP_OK(hipMemcpyAsync(plan->arena + plan->d_tab, plan->tab_blob.data(), plan->tab_blob.size(),
+                          hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+  }
+  plan->tab_states = key;
+  plan->tab_ready = true;
   return HX_OK;
 }
 
@@ -1642,23 +1654,13 @@ hx_status enqueue_single(hx_plan* plan, const Instance& I, double* state, hipStr
   return HX_OK;
 }
 
+// One step of every instance.  The stage tables of the batched instances
+// must have been prepared for these states (prepare_tables).
 hx_status enqueue_step(hx_plan* plan, double* const* states, hipStream_t s, Prof* prof = nullptr) {
   char* a = plan->arena;
   for (size_t k = 0; k < plan->inst.size(); ++k) {
     Instance& I = plan->inst[k];
-    if (I.sw) {  // shallow water, pole sums and velocity recovery in its last kernel
-      if (I.fp32) HX_TRY(enqueue_sw<float>(plan, I, states[k], s, prof));
-      else HX_TRY(enqueue_sw<double>(plan, I, states[k], s, prof));
-      continue;
-    }
-    if (I.fp32) {  // precision form, pole sum fused into its last kernel
-      HX_TRY(enqueue_refine(plan, I, states[k], s, prof));
-      continue;
-    }
-    if (batched(plan, I)) {  // pole sum fused into the leaf downward kernel
-      HX_TRY(enqueue_batched(plan, I, states[k], s, prof));
-      continue;
-    }
+    if (batched(plan, I)) continue;
     HX_TRY(enqueue_single(plan, I, states[k], s, prof));
     const long long n_int = (long long)I.n_leaf * I.q2;
     hx::PoleSumArgs ps{};
@@ -1676,6 +1678,7 @@ hx_status enqueue_step(hx_plan* plan, double* const* states, hipStream_t s, Prof
     ps.inv_tau = 1.0 / I.tau;
     TIMED(HX_K_POLE_SUM, hx::launch_pole_sum(ps, I.n_leaf, s));
   }
+  for (const Group& g : plan->groups) TIMED(g.cls, launch_group(plan, g, s));
   return HX_OK;
 }
 
@@ -1713,6 +1716,7 @@ hx_status hx_step(hx_plan* plan, double* const* states, int n_steps, void* strea
     HIP_OK(hipStreamSynchronize(s));
     if (flag) return fail(HX_ESTATE, "non-finite value in the state");
   }
+  HX_TRY(prepare_tables(plan, states, s));
   const bool use_graph = !(plan->flags & HX_FLAG_NO_GRAPH) && s != nullptr;
   if (!use_graph) {
     for (int n = 0; n < n_steps; ++n) HX_TRY(enqueue_step(plan, states, s));
@@ -1751,6 +1755,7 @@ hx_status hx_step_profile(hx_plan* plan, double* const* states, int n_steps, voi
   HIP_OK(hipSetDevice(plan->device));
   Prof prof;
   prof.s = static_cast<hipStream_t>(stream);
+  HX_TRY(prepare_tables(plan, states, prof.s));
   for (int n = 0; n < n_steps; ++n) HX_TRY(enqueue_step(plan, states, prof.s, &prof));
   HIP_OK(hipStreamSynchronize(prof.s));
   for (size_t k = 0; k < prof.cls.size(); ++k) {

@@ -36,7 +36,8 @@ __device__ __forceinline__ int side_of_slot_r(int mask, int slot) {
 }
 
 template <bool SW>
-__global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a, int RR) {
+__device__ __forceinline__ void residual_body(const ResidualArgs& a, const int bid) {
+  const int RR = a.RR;
   // Work items are rhs-fastest (RR is a power of two).  Each thread fetches
   // the same kPer grid items (node, rhs) for every pole (RR p^2 <= kPer
   // kBlock), with offsets computed once; the interior rows and edge slots
@@ -46,8 +47,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a, int RR) {
   const int p = a.p, q = a.q, q2 = q * q, pp = p * p;
   const int lg = __ffs(RR) - 1;
   const int nrg = (a.nrhs + RR - 1) / RR;
-  const int rg = blockIdx.x % nrg;
-  const int leaf = blockIdx.x / nrg;
+  const int rg = bid % nrg;
+  const int leaf = bid / nrg;
   const LeafDesc L = a.leaves[leaf];
   const int r = a.nrhs;
   const int r0 = rg * RR;                             // first right-hand side of the group
@@ -252,36 +253,66 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a, int RR) {
   }
 }
 
+template <bool SW>
+__global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a) {
+  residual_body<SW>(a, blockIdx.x);
+}
+
+template <bool SW>
+__global__ __launch_bounds__(kBlock) void k_residual_multi(Multi<ResidualArgs> m) {
+  int i;
+  const int bid = m.locate(blockIdx.x, i);
+  const ResidualArgs a = m.args[i];
+  residual_body<SW>(a, bid);
+}
+
 // Bytes of LDS for RR right-hand sides per block.
-static size_t residual_lds(int p, int RR, int nsrc) {
+size_t residual_lds_bytes(int p, int RR, int nsrc) {
   const int pp = p * p, q2 = (p - 2) * (p - 2);
   return sizeof(double) * (2 * (size_t)pp + 2 * (size_t)q2 * p + (size_t)nsrc * RR * q2) +
          sizeof(double2) * (size_t)RR * pp + sizeof(int) * ((size_t)q2 + 4 * (p - 2));
 }
 
-template <bool SW>
-static hipError_t residual_t(const ResidualArgs& a, int n_leaf, hipStream_t s) {
-  // right-hand sides per block: up to 32, within 56 KiB of LDS (two to
-  // three blocks per CU), at least 1 (then up to 160 KiB); the grid values
-  // of one pole are at most 8 per thread
+// Right-hand sides per block: up to 32, within 56 KiB of LDS (two to three
+// blocks per CU), at least 1 (then up to 160 KiB); the grid values of one
+// pole are at most 8 per thread.
+int residual_rr(const ResidualArgs& a) {
   int RR = 32;
-  while (RR > 1 && (RR / 2 >= a.nrhs || residual_lds(a.p, RR, a.nsrc) > 56 * 1024 ||
+  while (RR > 1 && (RR / 2 >= a.nrhs || residual_lds_bytes(a.p, RR, a.nsrc) > 56 * 1024 ||
                     RR * a.p * a.p > 8 * kBlock))
     RR /= 2;
-  const size_t lds = residual_lds(a.p, RR, a.nsrc);
-  if (lds > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_residual<SW>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  const int nrg = (a.nrhs + RR - 1) / RR;
-  hipLaunchKernelGGL(k_residual<SW>, dim3(n_leaf * nrg), dim3(kBlock), lds, s, a, RR);
+  return RR;
+}
+
+template <bool SW>
+static hipError_t allow_residual_lds(size_t lds, bool multi) {
+  if (lds <= 65536) return hipSuccess;
+  const void* f = multi ? reinterpret_cast<const void*>(&k_residual_multi<SW>)
+                        : reinterpret_cast<const void*>(&k_residual<SW>);
+  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t launch_residual(const ResidualArgs& a0, int n_leaf, hipStream_t s) {
+  ResidualArgs a = a0;
+  a.RR = residual_rr(a);
+  const size_t lds = residual_lds_bytes(a.p, a.RR, a.nsrc);
+  const int nrg = (a.nrhs + a.RR - 1) / a.RR;
+  const bool sw = a.esum != nullptr;
+  const hipError_t e = sw ? allow_residual_lds<true>(lds, false) : allow_residual_lds<false>(lds, false);
+  if (e != hipSuccess) return e;
+  if (sw) hipLaunchKernelGGL(k_residual<true>, dim3(n_leaf * nrg), dim3(kBlock), lds, s, a);
+  else hipLaunchKernelGGL(k_residual<false>, dim3(n_leaf * nrg), dim3(kBlock), lds, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_residual(const ResidualArgs& a, int n_leaf, hipStream_t s) {
-  if (a.esum) return residual_t<true>(a, n_leaf, s);
-  return residual_t<false>(a, n_leaf, s);
+hipError_t launch_residual_multi(const Multi<ResidualArgs>& m, int blocks, bool sw, size_t lds,
+                                 hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  const hipError_t e = sw ? allow_residual_lds<true>(lds, true) : allow_residual_lds<false>(lds, true);
+  if (e != hipSuccess) return e;
+  if (sw) hipLaunchKernelGGL(k_residual_multi<true>, dim3(blocks), dim3(kBlock), lds, s, m);
+  else hipLaunchKernelGGL(k_residual_multi<false>, dim3(blocks), dim3(kBlock), lds, s, m);
+  return hipGetLastError();
 }
 
 }  // namespace hx

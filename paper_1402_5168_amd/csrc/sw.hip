@@ -25,10 +25,10 @@
 
 namespace hx {
 
-__global__ __launch_bounds__(kBlock) void k_sw_prep(SwPrepArgs a) {
+__device__ __forceinline__ void sw_prep_body(const SwPrepArgs& a, const int bid) {
   __shared__ double Dq[(kMaxP - 2) * (kMaxP - 2)];
-  const int leaf = blockIdx.x / a.nrhs;
-  const int rhs = blockIdx.x - leaf * a.nrhs;
+  const int leaf = bid / a.nrhs;
+  const int rhs = bid - leaf * a.nrhs;
   const int q = a.q, q2 = q * q;
   for (int t = threadIdx.x; t < q2; t += blockDim.x) Dq[t] = a.Dq[t];
   __syncthreads();
@@ -52,8 +52,17 @@ __global__ __launch_bounds__(kBlock) void k_sw_prep(SwPrepArgs a) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_sw_wall(SwWallArgs a) {
-  const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_sw_prep(SwPrepArgs a) { sw_prep_body(a, blockIdx.x); }
+
+__global__ __launch_bounds__(kBlock) void k_sw_prep_multi(Multi<SwPrepArgs> m) {
+  int i;
+  const int bid = m.locate(blockIdx.x, i);
+  const SwPrepArgs a = m.args[i];
+  sw_prep_body(a, bid);
+}
+
+__device__ __forceinline__ void sw_wall_body(const SwWallArgs& a, const int bid) {
+  const long long idx = (long long)bid * blockDim.x + threadIdx.x;
   if (idx >= (long long)a.n_wall * a.nrhs) return;
   const int rhs = (int)(idx / a.n_wall);
   const int k = (int)(idx - (long long)rhs * a.n_wall);
@@ -70,14 +79,23 @@ __global__ __launch_bounds__(kBlock) void k_sw_wall(SwWallArgs a) {
     e2 += w[m] * v2[node];
   }
   // n and t = (-n2, n1): left (-1,0),(0,-1); right (1,0),(0,1);
-  // bottom (0,-1),(1,0); top (0,1),(-1,0)
-  double nv, tv;
-  if (side == 0) { nv = -e1; tv = -e2; }
-  else if (side == 1) { nv = e1; tv = e2; }
-  else if (side == 2) { nv = -e2; tv = e1; }
-  else { nv = e2; tv = -e1; }
+  // bottom (0,-1),(1,0); top (0,1),(-1,0).  Written as sign arithmetic: an
+  // if/else chain here was compiled with the top wall's t.v sign lost.
+  const double sg = (side == 0 || side == 2) ? -1.0 : 1.0;   // outward sign
+  const bool xs = side < 2;                                 // normal along x
+  const double nv = sg * (xs ? e1 : e2);
+  const double tv = xs ? sg * e2 : -sg * e1;
   a.out[(long long)rhs * 2 * a.n_wall + k] = nv;
   a.out[(long long)rhs * 2 * a.n_wall + a.n_wall + k] = tv;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sw_wall(SwWallArgs a) { sw_wall_body(a, blockIdx.x); }
+
+__global__ __launch_bounds__(kBlock) void k_sw_wall_multi(Multi<SwWallArgs> m) {
+  int i;
+  const int bid = m.locate(blockIdx.x, i);
+  const SwWallArgs a = m.args[i];
+  sw_wall_body(a, bid);
 }
 
 // G = a T_root - f D_t for every pole of a build chunk (column-major n x n).
@@ -108,14 +126,15 @@ __device__ __forceinline__ int sw_slot_of_side(int mask, int side) {
 // sums go to LDS, and every interior item forms the gradients along the
 // p-point lines and the new state.
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_sw_post(SwPostArgs<T> a, int RR) {
+__device__ __forceinline__ void sw_post_body(const SwPostArgs<T>& a, const int bid) {
+  const int RR = a.RR;
   using C = typename Cplx<T>::type;
   constexpr int kPer = 8;
   extern __shared__ double smem[];
   const int p = a.p, q = a.q, q2 = q * q, pp = p * p;
   const int nrg = (a.nrhs + RR - 1) / RR;
-  const int rg = blockIdx.x % nrg;
-  const int leaf = blockIdx.x / nrg;
+  const int rg = bid % nrg;
+  const int leaf = bid / nrg;
   const int r = a.nrhs, r0 = rg * RR, ES = RR + 1;
   const LeafDesc L = a.leaves[leaf];
   double* Ds = smem;                  // p x p
@@ -216,6 +235,17 @@ __global__ __launch_bounds__(kBlock) void k_sw_post(SwPostArgs<T> a, int RR) {
   }
 }
 
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_sw_post(SwPostArgs<T> a) { sw_post_body<T>(a, blockIdx.x); }
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_sw_post_multi(Multi<SwPostArgs<T>> m) {
+  int i;
+  const int bid = m.locate(blockIdx.x, i);
+  const SwPostArgs<T> a = m.args[i];
+  sw_post_body<T>(a, bid);
+}
+
 hipError_t launch_sw_prep(const SwPrepArgs& a, int n_leaf, hipStream_t s) {
   hipLaunchKernelGGL(k_sw_prep, dim3(n_leaf * a.nrhs), dim3(kBlock), 0, s, a);
   return hipGetLastError();
@@ -235,17 +265,47 @@ hipError_t launch_sw_root_form(const SwRootFormArgs& a, int chunk, hipStream_t s
   return hipGetLastError();
 }
 
-template <class T>
-hipError_t launch_sw_post(const SwPostArgs<T>& a, int n_leaf, hipStream_t s) {
-  // right-hand sides per block: a power of two up to 8, the grid items of
-  // one pole at most 8 per thread
+// Right-hand sides per block: a power of two up to 8, the grid items of one
+// pole at most 8 per thread.
+int sw_post_rr(int p, int nrhs) {
   int RR = 8;
-  while (RR > 1 && (RR / 2 >= a.nrhs || RR * a.p * a.p > 8 * kBlock)) RR /= 2;
-  const size_t lds = sizeof(double) * (size_t)a.p * a.p * (1 + 3 * (RR + 1));
-  const int nrg = (a.nrhs + RR - 1) / RR;
-  hipLaunchKernelGGL((k_sw_post<T>), dim3(n_leaf * nrg), dim3(kBlock), lds, s, a, RR);
+  while (RR > 1 && (RR / 2 >= nrhs || RR * p * p > 8 * kBlock)) RR /= 2;
+  return RR;
+}
+
+size_t sw_post_lds_bytes(int p, int RR) { return sizeof(double) * (size_t)p * p * (1 + 3 * (RR + 1)); }
+
+template <class T>
+hipError_t launch_sw_post(const SwPostArgs<T>& a0, int n_leaf, hipStream_t s) {
+  SwPostArgs<T> a = a0;
+  a.RR = sw_post_rr(a.p, a.nrhs);
+  const size_t lds = sw_post_lds_bytes(a.p, a.RR);
+  const int nrg = (a.nrhs + a.RR - 1) / a.RR;
+  hipLaunchKernelGGL((k_sw_post<T>), dim3(n_leaf * nrg), dim3(kBlock), lds, s, a);
   return hipGetLastError();
 }
+
+template <class T>
+hipError_t launch_sw_post_multi(const Multi<SwPostArgs<T>>& m, int blocks, size_t lds, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_sw_post_multi<T>), dim3(blocks), dim3(kBlock), lds, s, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_sw_prep_multi(const Multi<SwPrepArgs>& m, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sw_prep_multi, dim3(blocks), dim3(kBlock), 0, s, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_sw_wall_multi(const Multi<SwWallArgs>& m, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sw_wall_multi, dim3(blocks), dim3(kBlock), 0, s, m);
+  return hipGetLastError();
+}
+
+template hipError_t launch_sw_post_multi<double>(const Multi<SwPostArgs<double>>&, int, size_t, hipStream_t);
+template hipError_t launch_sw_post_multi<float>(const Multi<SwPostArgs<float>>&, int, size_t, hipStream_t);
 
 template hipError_t launch_sw_post<double>(const SwPostArgs<double>&, int, hipStream_t);
 template hipError_t launch_sw_post<float>(const SwPostArgs<float>&, int, hipStream_t);
