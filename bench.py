@@ -244,13 +244,139 @@ def run(w, precision: str, unbatched: bool, steps: int, warmup: int, profile: bo
     return out, final
 
 
+def run_batch(args):
+    """Batching form: instances of the batch recipe, in order, as many as
+    fit the arena budget, stepped as ONE plan (one fused launch per stage
+    over all instances, replayed from a hipGraph), then each instance in a
+    plan of its own, stepped one after the other, for the comparison."""
+    import numpy as np
+    import torch
+
+    from paper_1402_5168_amd import hpsexp
+    from workloads import configs
+
+    rec = configs.BATCH_RECIPES[args.workload]
+    prec = hpsexp.HX_FP32_REFINE if args.precision == "fp32-refine" else hpsexp.HX_FP64
+    flags = hpsexp.HX_FLAG_AUTOTUNE if args.autotune else 0
+    budget = args.budget_gb * 2 ** 30
+
+    def add(plan, w):
+        m = w.mesh
+        return plan.add(m.nex, m.ney, m.p, w.c2, w.tau, configs.DELTA, w.fit.alpha, w.fit.b,
+                        nrhs=w.u0.shape[0])
+
+    ws, total = [], 0
+    for i in range(args.max_instances or rec.n_instances):
+        w = configs.batch_instance(rec, i)
+        probe = hpsexp.Plan(device=0, precision=prec)
+        add(probe, w)
+        need = probe.query()["arena_bytes"]
+        probe.close()
+        if total + need > budget:
+            break
+        ws.append(w)
+        total += need
+
+    def timed(plans, states, steps, warmup):
+        stream = torch.cuda.Stream(device=0)
+        with torch.cuda.stream(stream):
+            for pl, st in zip(plans, states):
+                pl.step(st, warmup, stream=stream)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                for pl, st in zip(plans, states):
+                    pl.step(st, 1, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+        return e0.elapsed_time(e1), stream
+
+    plan = hpsexp.Plan(device=0, precision=prec, flags=flags)
+    for w in ws:
+        add(plan, w)
+    info = plan.query()
+    plan.bind()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.build()
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    states = [torch.tensor(w.state(), device="cuda:0") for w in ws]
+    ms, stream = timed([plan], [states], args.steps, args.warmup)
+    finals = [x.cpu().numpy() for x in states]
+    kms, nl = plan.step_profile(states, max(args.steps // 2, 1), stream=stream)
+    tiles = [plan.tiles(k) for k in range(len(ws))]
+    plan.close()
+    del states
+    torch.cuda.empty_cache()
+    ms_step = ms / args.steps
+    value = info["dof_state"] * 1e3 / ms_step
+    kernels = {}
+    for k, name in enumerate(hpsexp.KERNEL_NAMES):
+        if nl[k]:
+            kernels[name] = {"launches": nl[k], "ms_total": kms[k], "ms_avg": kms[k] / nl[k]}
+    flops = sum(8.0 * w.mesh.n_el * w.mesh.q ** 4 * (w.fit.M + 1) * w.u0.shape[0] for w in ws)
+    lu = kernels["k_leaf_up"]
+    tf = flops / (lu["ms_avg"] * 1e-3) / 1e12
+    peak = FP32_PEAK_TFLOPS if prec == hpsexp.HX_FP32_REFINE else FP64_PEAK_TFLOPS
+    # the same instances, each in its own plan, stepped one after the other
+    seq_ms = None
+    if not args.no_compare:
+        plans, sts = [], []
+        for w in ws:
+            pl = hpsexp.Plan(device=0, precision=prec)
+            add(pl, w)
+            pl.bind()
+            pl.build()
+            plans.append(pl)
+            sts.append([torch.tensor(w.state(), device="cuda:0")])
+        seq, _ = timed(plans, sts, args.steps, args.warmup)
+        seq_ms = seq / args.steps
+        err = 0.0
+        for k, st in enumerate(sts):
+            err = max(err, float(np.abs(st[0].cpu().numpy() - finals[k]).max()))
+        for pl in plans:
+            pl.close()
+        del sts
+    sides = {}
+    for w in ws:
+        sides[w.mesh.nex] = sides.get(w.mesh.nex, 0) + 1
+    out = {
+        "metric": METRIC, "value": value, "unit": "DOF·steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if prec == hpsexp.HX_FP32_REFINE else "f64", "data": "synthetic",
+        "config": {"workload": f"{rec.name}: first {len(ws)} of {rec.n_instances} instances "
+                               f"(arena budget {args.budget_gb} GiB)",
+                   "instances": len(ws), "elements_per_side": sides, "p": rec.p,
+                   "rhs_total": int(sum(w.u0.shape[0] for w in ws)),
+                   "folded_poles_total": int(sum(w.fit.M + 1 for w in ws)),
+                   "precision": args.precision, "autotune": bool(args.autotune),
+                   "dof_state": info["dof_state"], "operator_GiB": info["operator_bytes"] / 2 ** 30,
+                   "arena_GiB": info["arena_bytes"] / 2 ** 30},
+        "build_s": build_s,
+        "roofline": {"bound": "mfma", "kernel": "k_leaf_up", "achieved": tf, "peak": peak,
+                     "unit": "TFLOP/s", "frac": tf / peak, "traffic": None},
+        "kernels": kernels,
+        "tiles_first_instances": {"stages": "leaf_up, merge_up, root, merge_down, leaf_down",
+                                  "tiles": tiles[:6]},
+    }
+    if seq_ms is not None:
+        out["compare"] = {"separate_plans_ms_per_step": seq_ms,
+                          "speedup_fused_vs_separate": seq_ms / ms_step,
+                          "max_abs_diff_fused_vs_separate": err}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="wave_64x64_p10",
-                    help="wave_4x4_p12, wave_32x32_p16, wave_64x64_p10 or sw_32x32_p12")
+                    help="wave_4x4_p12, wave_32x32_p16, wave_64x64_p10, sw_32x32_p12 or batch_512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP64 runs of the same workload")
@@ -259,6 +385,12 @@ def main():
     ap.add_argument("--unbatched", action="store_true",
                     help="one pass per right-hand side (reference for the batching speedup)")
     ap.add_argument("--precision", choices=["fp64", "fp32-refine"], default="fp32-refine")
+    ap.add_argument("--budget-gb", type=float, default=120.0,
+                    help="batch workloads: arena budget for the instances taken")
+    ap.add_argument("--max-instances", type=int, default=None,
+                    help="batch workloads: at most this many instances")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="batch workloads: tune the tile count per stage at build (1) or not (0)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -269,6 +401,9 @@ def main():
 
     from workloads import configs
 
+    if args.workload in configs.BATCH_RECIPES:
+        run_batch(args)
+        return
     sw = args.workload in configs.SW_RECIPES
     if sw:
         rec = configs.SW_RECIPES[args.workload]

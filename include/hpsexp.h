@@ -97,6 +97,10 @@ typedef enum {
 #define HX_FLAG_UNBATCHED      0x8u /* one pass per right-hand side instead of
                                        batching them on the matrix cores
                                        (reference for the batching speedup)  */
+#define HX_FLAG_AUTOTUNE       0x10u /* hx_plan_build times each batched
+                                        instance's stages with one and two
+                                        right-hand-side tiles per block and
+                                        keeps the faster (hx_plan_tiles)     */
 
 /* Mesh: [x0,x1] x [y0,y1] split into nex x ney equal elements, each with a
  * p x p Chebyshev-Lobatto grid (section 2.2).  nex and ney are powers of
@@ -216,6 +220,21 @@ hx_status hx_step(hx_plan* plan, double* const* states, int n_steps, void* strea
  * Synchronous.  Errors as hx_step. */
 hx_status hx_step_profile(hx_plan* plan, double* const* states, int n_steps, void* stream,
                           double* kernel_ms, int* launches, int n_classes);
+
+/* Stages whose right-hand-side tile count (1 or 2 tiles of 16 columns per
+ * block) is chosen per instance, by the default rule (2 when nrhs > 16)
+ * or by the autotuner. */
+#define HX_STAGE_LEAF_UP    0  /* element upward pass                          */
+#define HX_STAGE_MERGE_UP   1  /* merge upward passes                          */
+#define HX_STAGE_ROOT       2  /* shallow-water root system                    */
+#define HX_STAGE_MERGE_DOWN 3  /* merge downward passes                        */
+#define HX_STAGE_LEAF_DOWN  4  /* element downward pass (and fused pole sum)   */
+#define HX_STAGES           5
+
+/* Tile counts in use for instance `instance`: tiles[s] for the first
+ * min(n, HX_STAGES) stages (host array).  0 for an instance that runs one
+ * pass per right-hand side.  HX_EINVAL for a bad instance id. */
+hx_status hx_plan_tiles(const hx_plan* plan, int instance, int* tiles, int n);
 
 /* Name of a status code. */
 const char* hx_status_str(int status);

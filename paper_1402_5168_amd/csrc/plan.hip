@@ -830,6 +830,10 @@ hx_status build_chunk(Build& B, Instance& I, const WsLayout& W, int p0, int ch) 
   return HX_OK;
 }
 
+// defined with the step code below
+void drop_graph(hx_plan* plan);
+hx_status autotune(hx_plan* plan, char* ws, size_t ws_bytes, hipStream_t s);
+
 }  // namespace
 
 // ============================================================================
@@ -861,7 +865,8 @@ hx_status hx_plan_create(hx_plan** out, int precision, int device, unsigned flag
   if (precision != HX_FP64 && precision != HX_FP32_REFINE)
     return fail(HX_EINVAL, "unsupported precision %d", precision);
   if (device < 0) return fail(HX_EINVAL, "device %d", device);
-  if (flags & ~(HX_FLAG_ALLOW_UNSTABLE | HX_FLAG_NO_GRAPH | HX_FLAG_CHECK_STATE | HX_FLAG_UNBATCHED))
+  if (flags & ~(HX_FLAG_ALLOW_UNSTABLE | HX_FLAG_NO_GRAPH | HX_FLAG_CHECK_STATE | HX_FLAG_UNBATCHED |
+                HX_FLAG_AUTOTUNE))
     return fail(HX_EINVAL, "unknown flags 0x%x", flags);
   hx_plan* p = new hx_plan;
   p->device = device;
@@ -1102,6 +1107,9 @@ hx_status hx_plan_build(hx_plan* plan, void* workspace, size_t workspace_bytes, 
     for (int p0 = 0; p0 < I.npole; p0 += ch) HX_TRY(build_chunk(B, I, W, p0, std::min(ch, I.npole - p0)));
   }
   HIP_OK(hipStreamSynchronize(B.s));
+  drop_graph(plan);
+  plan->tab_ready = false;
+  if (plan->flags & HX_FLAG_AUTOTUNE) HX_TRY(autotune(plan, B.ws, B.ws_bytes, B.s));
   plan->built = true;
   return HX_OK;
 }
@@ -1569,6 +1577,75 @@ hx_status prepare_tables(hx_plan* plan, double* const* states, hipStream_t s) {
   return HX_OK;
 }
 
+// Stages the tile count is tuned for (stage order of the recorder), in the
+// order of the HX_STAGE_* codes.
+constexpr int kTunedOrders[HX_STAGES] = {O_LEAF_UP, O_MERGE_UP, O_ROOT, O_MERGE_DOWN, O_LEAF_DOWN};
+
+// Autotuner: for every batched instance with more than 16 right-hand sides
+// and every tuned stage, launch that stage of the first sweep (all its
+// levels) with one and with two tiles per block on a scratch state in the
+// build workspace, time the better of three runs of each, keep the faster.
+template <class T>
+hx_status tune_instance(hx_plan* plan, Instance& I, int k, double* scratch, hipStream_t s,
+                        hipEvent_t e0, hipEvent_t e1) {
+  for (int st = 0; st < HX_STAGES; ++st) {
+    const int order = kTunedOrders[st];
+    float best = 1e30f;
+    int best_nt = 0;
+    for (int nt = 1; nt <= 2; ++nt) {
+      I.tune_nt[order] = nt;
+      Recorder R;
+      record_instance<T>(plan, I, k, scratch, R);
+      Recorder one;
+      for (const Rec& r : R.recs)
+        if (r.pass == 0 && r.order == order) one.recs.push_back(r);
+      if (one.recs.empty()) break;
+      std::vector<Group> groups;
+      std::vector<unsigned char> blob;
+      group_stages(one, groups, blob);
+      if (blob.size() > plan->tab_bytes) break;
+      HIP_OK(hipMemcpyAsync(plan->arena + plan->d_tab, blob.data(), blob.size(), hipMemcpyHostToDevice, s));
+      HIP_OK(hipStreamSynchronize(s));
+      float t_min = 1e30f;
+      for (int rep = 0; rep < 4; ++rep) {   // the first run warms up
+        HIP_OK(hipEventRecord(e0, s));
+        for (const Group& g : groups) HIP_OK(launch_group(plan, g, s));
+        HIP_OK(hipEventRecord(e1, s));
+        HIP_OK(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+        if (rep > 0) t_min = std::min(t_min, ms);
+      }
+      if (t_min < best) {
+        best = t_min;
+        best_nt = nt;
+      }
+    }
+    I.tune_nt[order] = best_nt;
+  }
+  return HX_OK;
+}
+
+hx_status autotune(hx_plan* plan, char* ws, size_t ws_bytes, hipStream_t s) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  struct EvGuard { hipEvent_t a, b; ~EvGuard() { hipEventDestroy(a); hipEventDestroy(b); } } g{e0, e1};
+  hx_status st = HX_OK;
+  for (size_t k = 0; k < plan->inst.size() && st == HX_OK; ++k) {
+    Instance& I = plan->inst[k];
+    if (!batched(plan, I) || I.nrhs <= 16) continue;
+    const size_t need = sizeof(double) * (size_t)I.nfield * I.n_leaf * I.q2 * I.nrhs;
+    if (need > ws_bytes) continue;                 // no room for a scratch state: default rule
+    double* scratch = reinterpret_cast<double*>(ws);
+    HIP_OK(hipMemsetAsync(scratch, 0, need, s));
+    st = I.fp32 ? tune_instance<float>(plan, I, (int)k, scratch, s, e0, e1)
+                : tune_instance<double>(plan, I, (int)k, scratch, s, e0, e1);
+  }
+  plan->tab_ready = false;                         // the tables now hold tuning stages
+  return st;
+}
+
 hx_status enqueue_single(hx_plan* plan, const Instance& I, double* state, hipStream_t s, Prof* prof) {
   char* a = plan->arena;
   const double2* ops = reinterpret_cast<const double2*>(a + I.d_ops);
@@ -1767,6 +1844,17 @@ hx_status hx_step_profile(hx_plan* plan, double* const* states, int n_steps, voi
       launches[c] += 1;
     }
   }
+  return HX_OK;
+}
+
+hx_status hx_plan_tiles(const hx_plan* plan, int instance, int* tiles, int n) {
+  g_last_error.clear();
+  if (!plan || !tiles) return fail(HX_EINVAL, "null plan or tiles");
+  if (instance < 0 || instance >= (int)plan->inst.size())
+    return fail(HX_EINVAL, "instance %d of %zu", instance, plan->inst.size());
+  const Instance& I = plan->inst[instance];
+  for (int st = 0; st < std::min(n, (int)HX_STAGES); ++st)
+    tiles[st] = batched(plan, I) ? stage_nt(I, kTunedOrders[st]) : 0;
   return HX_OK;
 }
 

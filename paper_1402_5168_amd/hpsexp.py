@@ -23,6 +23,7 @@ HX_EUNSTABLE, HX_EDEVICE, HX_ESTATE, HX_ESTAGE = -4, -5, -6, -7
 HX_WAVE_DIRICHLET, HX_SW_SLIP = 0, 1
 HX_FP64, HX_FP32_REFINE = 0, 1
 HX_FLAG_ALLOW_UNSTABLE, HX_FLAG_NO_GRAPH, HX_FLAG_CHECK_STATE, HX_FLAG_UNBATCHED = 0x1, 0x2, 0x4, 0x8
+HX_FLAG_AUTOTUNE = 0x10
 
 
 class hx_mesh(ctypes.Structure):
@@ -53,8 +54,11 @@ HX_K_CLASSES = 8
 KERNEL_NAMES = ("k_leaf_up", "k_merge_up", "k_merge_down", "k_leaf_down", "k_pole_sum",
                 "k_residual", "k_sw_prep", "k_sw_root")
 
+HX_STAGE_LEAF_UP, HX_STAGE_MERGE_UP, HX_STAGE_ROOT, HX_STAGE_MERGE_DOWN, HX_STAGE_LEAF_DOWN = range(5)
+HX_STAGES = 5
+
 EXPORTS = ("hx_plan_create", "hx_plan_add", "hx_plan_query", "hx_plan_bind",
-           "hx_plan_build", "hx_step", "hx_step_profile", "hx_status_str",
+           "hx_plan_build", "hx_step", "hx_step_profile", "hx_plan_tiles", "hx_status_str",
            "hx_last_error", "hx_plan_destroy")
 
 _lib = None
@@ -78,13 +82,14 @@ def load() -> ctypes.CDLL:
     lib.hx_step.argtypes = [c_void_p, POINTER(c_void_p), c_int, c_void_p]
     lib.hx_step_profile.argtypes = [c_void_p, POINTER(c_void_p), c_int, c_void_p,
                                     POINTER(c_double), POINTER(c_int), c_int]
+    lib.hx_plan_tiles.argtypes = [c_void_p, c_int, POINTER(c_int), c_int]
     lib.hx_status_str.argtypes = [c_int]
     lib.hx_status_str.restype = c_char_p
     lib.hx_last_error.argtypes = []
     lib.hx_last_error.restype = c_char_p
     lib.hx_plan_destroy.argtypes = [c_void_p]
     lib.hx_plan_destroy.restype = None
-    for name in EXPORTS[:7]:
+    for name in EXPORTS[:8]:
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -144,6 +149,12 @@ def hx_step_profile(plan, state_ptrs, n_steps: int, stream: int = 0):
     nl = (c_int * HX_K_CLASSES)()
     _check(load().hx_step_profile(plan, arr, n_steps, c_void_p(stream), ms, nl, HX_K_CLASSES))
     return list(ms), list(nl)
+
+
+def hx_plan_tiles(plan, instance: int):
+    t = (c_int * HX_STAGES)()
+    _check(load().hx_plan_tiles(plan, instance, t, HX_STAGES))
+    return list(t)
 
 
 def hx_status_str(status: int) -> str:
@@ -234,6 +245,10 @@ class Plan:
                 raise ValueError(f"state {k} has shape {tuple(x.shape)}, "
                                  f"expected {self.state_shape(k)}")
         hx_step(self.handle, [x.data_ptr() for x in states], n_steps, s.cuda_stream)
+
+    def tiles(self, k: int):
+        """Right-hand-side tiles per block of instance k, per HX_STAGE_*."""
+        return hx_plan_tiles(self.handle, k)
 
     def step_profile(self, states, n_steps: int, stream=None):
         import torch

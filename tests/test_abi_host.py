@@ -155,3 +155,17 @@ def test_shallow_water_add_validation_and_sizes():
     sw()
     assert plan.query()["operator_bytes"] * 2 == info["operator_bytes"]
     plan.close()
+
+
+def test_tile_counts_default_rule():
+    plan = hx.Plan()
+    a = _add(plan, nex=2, ney=2, p=6, nrhs=1)          # one pass per RHS: no tiles
+    b = _add(plan, nex=2, ney=2, p=6, nrhs=3)
+    c = _add(plan, nex=2, ney=2, p=6, nrhs=20)
+    assert plan.tiles(a) == [0] * hx.HX_STAGES
+    assert plan.tiles(b) == [1] * hx.HX_STAGES
+    assert plan.tiles(c) == [2] * hx.HX_STAGES
+    assert status_of(lambda: plan.tiles(3)) == hx.HX_EINVAL
+    plan.close()
+    assert status_of(lambda: hx.hx_plan_create(hx.HX_FP64, 0, 0x40)) == hx.HX_EINVAL
+    hx.hx_plan_destroy(hx.hx_plan_create(hx.HX_FP64, 0, hx.HX_FLAG_AUTOTUNE))

@@ -88,3 +88,40 @@ def test_fused_graph_equals_eager():
     e = run(ws, 4, 1, flags=hpsexp.HX_FLAG_NO_GRAPH)
     for a, b in zip(g, e):
         assert np.array_equal(a, b)
+
+
+def test_autotuned_plan_equals_default_plan():
+    """The autotuner only changes how many 16-column tiles a block takes;
+    every column's arithmetic and order stay the same, so the results are
+    bit-identical to the default tile rule."""
+    say("6 instances, precision form, autotuned tiles vs default tiles")
+    torch = _torch()
+    from paper_1402_5168_amd import hpsexp
+    ws = batch()
+    tuned = hpsexp.Plan(device=0, precision=1, flags=hpsexp.HX_FLAG_AUTOTUNE)
+    for w in ws:
+        m = w.mesh
+        if isinstance(w, configs.SWInputs):
+            tuned.add_sw(m.nex, m.ney, m.p, w.recipe.f, w.recipe.gH, w.tau, 1e-10, w.fit.alpha,
+                         w.fit.b, nrhs=w.state().shape[0])
+        else:
+            tuned.add(m.nex, m.ney, m.p, w.c2, w.tau, 1e-10, w.fit.alpha, w.fit.b,
+                      nrhs=w.state().shape[0])
+    tuned.bind()
+    tuned.build()
+    tiles = [tuned.tiles(k) for k in range(len(ws))]
+    say(f"tiles per instance: {tiles}")
+    for k, w in enumerate(ws):
+        assert all(t in (1, 2) for t in tiles[k])
+        if w.state().shape[0] <= 16:
+            assert tiles[k] == [1] * hpsexp.HX_STAGES
+    states = [torch.tensor(w.state(), device="cuda:0") for w in ws]
+    stream = torch.cuda.Stream(device=0)
+    with torch.cuda.stream(stream):
+        tuned.step(states, 3, stream=stream)
+    stream.synchronize()
+    got = [x.cpu().numpy() for x in states]
+    tuned.close()
+    ref = run(ws, 3, 1)
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)

@@ -190,3 +190,48 @@ def scaled_sw(recipe: SWRecipe | str, nex: int, ney: int, p: int | None = None,
         mesh=layout.Mesh(nex, ney, p or m.p, m.x0, m.x1, m.y0, m.y1),
         npoles=npoles or recipe.npoles, kmax=kmax or recipe.kmax,
         n_steps=n_steps or recipe.n_steps)
+
+
+# ---- batching form: many wave instances of uneven size ------------------------------
+
+
+@dataclasses.dataclass(frozen=True)
+class BatchRecipe:
+    """Wave instances of uneven size stepped together (the batching form).
+
+    Instance i: sides[i % 3] x sides[i % 3] elements of p x p nodes; a
+    clipped-lognormal speed with seed i; pole count drawn uniformly from
+    `poles` and 1..max_rhs right-hand sides, both from the generator
+    seeded 1000 + i; Gaussian pulses with seeds 16 i + j; tau by the pulse
+    rule for its own pole count and speed.  Reading: the pole counts are the
+    calibrated odd counts in 41..101 (41, 61, 81, 101)."""
+    name: str
+    n_instances: int
+    sides: tuple = (8, 16, 32)
+    p: int = 12
+    poles: tuple = (41, 61, 81, 101)
+    max_rhs: int = 16
+    pulse_width: float = 0.05
+    n_steps: int = 10
+
+
+BATCH_RECIPES = {
+    "batch_512": BatchRecipe("batch_512", 512),
+}
+
+
+def batch_instance(recipe: BatchRecipe, i: int) -> WaveInputs:
+    rng = np.random.default_rng(1000 + i)
+    npoles = int(rng.choice(recipe.poles))
+    nrhs = int(rng.integers(1, recipe.max_rhs + 1))
+    side = recipe.sides[i % len(recipe.sides)]
+    rec = WaveRecipe(f"{recipe.name}[{i}]", layout.Mesh(side, side, recipe.p),
+                     "clipped_lognormal", i, npoles, None,
+                     tuple(16 * i + j for j in range(nrhs)), recipe.pulse_width, recipe.n_steps)
+    return make(rec)
+
+
+def make_batch(recipe: BatchRecipe | str, n: int | None = None) -> list:
+    if isinstance(recipe, str):
+        recipe = BATCH_RECIPES[recipe]
+    return [batch_instance(recipe, i) for i in range(n or recipe.n_instances)]

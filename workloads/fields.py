@@ -40,6 +40,15 @@ class FourierFeatureField:
         x = np.asarray(x, dtype=np.float64)
         y = np.asarray(y, dtype=np.float64)
         flat_x, flat_y = x.reshape(-1), y.reshape(-1)
+        ux, ix = np.unique(flat_x, return_inverse=True)
+        uy, iy = np.unique(flat_y, return_inverse=True)
+        if ux.size * uy.size <= 4 * flat_x.size:
+            # points on a tensor grid: cos(a + b) = cos a cos b - sin a sin b
+            # with a = w1 x + phi, b = w2 y makes the sum one matrix product
+            a = np.outer(ux, self.w[:, 0]) + self.phi
+            b = np.outer(uy, self.w[:, 1])
+            grid = np.cos(a) @ np.cos(b).T - np.sin(a) @ np.sin(b).T
+            return (self.scale * grid[ix, iy]).reshape(x.shape)
         out = np.empty(flat_x.shape)
         step = 65536
         for s in range(0, flat_x.size, step):

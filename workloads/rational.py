@@ -92,6 +92,8 @@ ETA_TABLE1 = 4.315321510875024
 CALIBRATED = {
     21: (ETA_TABLE1, 3.0, 2000),
     41: (5.0, 10.0, 2000),
+    61: (5.5, 16.0, None),
+    81: (5.5, 26.0, None),
     101: (6.0, 34.0, None),
     131: (6.0, 48.0, None),
 }
