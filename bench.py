@@ -391,7 +391,18 @@ def main():
                     help="batch workloads: at most this many instances")
     ap.add_argument("--autotune", type=int, default=1,
                     help="batch workloads: tune the tile count per stage at build (1) or not (0)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device to device once (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        x = torch.ones(2 ** 28, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(pole-sharded multi-GPU stepping is not part of this build)", file=sys.stderr)

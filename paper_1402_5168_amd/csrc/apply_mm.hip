@@ -215,6 +215,9 @@ __device__ __forceinline__ void leaf_up_body(const MmLeafUpArgs<T>& a, const int
   __syncthreads();
   const C* W = a.ops + pole * a.pole_stride + L.op_off;
   C* w = a.w + ((long long)pole * a.w_pole + (long long)leaf * q2) * r;
+  // with w_lds the block also keeps its w tile [q^2][RT] in LDS after the
+  // staged g, so that h = N_i w does not read w back from memory
+  C* wl = gs + q2p * BST;
   const int wave = threadIdx.x >> 6;
   for (int tile = wave; tile * 16 < q2; tile += kBlock / 64) {
     Acc<T, NT> acc;
@@ -223,6 +226,7 @@ __device__ __forceinline__ void leaf_up_body(const MmLeafUpArgs<T>& a, const int
     mm_emit<T, NT>(acc, tile * 16, q2, [&](int row, int j, C c) {
       const int rhs = rt * RT + j;
       if (rhs < r) w[(long long)row * r + rhs] = c;
+      if (a.w_lds) wl[row * RT + j] = c;
     });
   }
   __syncthreads();
@@ -241,7 +245,7 @@ __device__ __forceinline__ void leaf_up_body(const MmLeafUpArgs<T>& a, const int
     T sx_ = T(0), sy_ = T(0);
     for (int k = 0; k < q; ++k) {
       const int node = (s < 2) ? (k + q * t) : (t + q * k);
-      const C wv = w[(long long)node * r + rhs];
+      const C wv = a.w_lds ? wl[node * RT + j] : w[(long long)node * r + rhs];
       sx_ += T(nr[k]) * wv.x;
       sy_ += T(nr[k]) * wv.y;
     }
@@ -666,8 +670,9 @@ template hipError_t launch_sw_root_mm<float>(const SwRootArgs<float>&, hipStream
 // ---- launchers -----------------------------------------------------------------
 
 template <class T, int NT>
-size_t leaf_up_lds(int q) {
-  return sizeof(typename MM<T>::C) * (size_t)((q * q + 3) & ~3) * (16 * NT + 1);
+size_t leaf_up_lds(int q, bool with_w = false) {
+  return sizeof(typename MM<T>::C) *
+         ((size_t)((q * q + 3) & ~3) * (16 * NT + 1) + (with_w ? (size_t)q * q * 16 * NT : 0));
 }
 
 template <class T, int NT>
@@ -735,8 +740,8 @@ hipError_t launch_leaf_down_sum_mm(const MmLeafDownArgs<T>& a, int n_leaf, int n
 // ---- multi-instance launchers ------------------------------------------------------
 
 template <class T>
-size_t leaf_up_lds_bytes(int q, int nt) {
-  return nt == 2 ? leaf_up_lds<T, 2>(q) : leaf_up_lds<T, 1>(q);
+size_t leaf_up_lds_bytes(int q, int nt, bool with_w) {
+  return nt == 2 ? leaf_up_lds<T, 2>(q, with_w) : leaf_up_lds<T, 1>(q, with_w);
 }
 
 template <class K>
@@ -777,14 +782,52 @@ HX_MULTI_LAUNCHER(leaf_down_sum_mm, MmLeafDownArgs)
 HX_MULTI_LAUNCHER(sw_root_mm, SwRootArgs)
 #undef HX_MULTI_LAUNCHER
 
+// Single-instance launches with the arguments by value (a group of one
+// instance skips the table lookup), same block counts as the multi form.
+template <class T>
+hipError_t launch_leaf_up_mm_one(const MmLeafUpArgs<T>& a, int blocks, int nt, size_t lds, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  if (nt == 2) {
+    const hipError_t e = allow_lds(&k_leaf_up_mm<T, 2>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_leaf_up_mm<T, 2>), dim3(blocks), dim3(kBlock), lds, s, a);
+  } else {
+    const hipError_t e = allow_lds(&k_leaf_up_mm<T, 1>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_leaf_up_mm<T, 1>), dim3(blocks), dim3(kBlock), lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+#define HX_ONE_LAUNCHER(NAME, ARGS)                                                            \
+  template <class T>                                                                           \
+  hipError_t launch_##NAME##_one(const ARGS<T>& a, int blocks, int nt, hipStream_t s) {        \
+    if (blocks <= 0) return hipSuccess;                                                        \
+    if (nt == 2) hipLaunchKernelGGL((k_##NAME<T, 2>), dim3(blocks), dim3(kBlock), 0, s, a);    \
+    else hipLaunchKernelGGL((k_##NAME<T, 1>), dim3(blocks), dim3(kBlock), 0, s, a);           \
+    return hipGetLastError();                                                                  \
+  }
+HX_ONE_LAUNCHER(merge_up_mm, MmMergeArgs)
+HX_ONE_LAUNCHER(merge_down_mm, MmMergeArgs)
+HX_ONE_LAUNCHER(leaf_down_mm, MmLeafDownArgs)
+HX_ONE_LAUNCHER(leaf_down_sum_mm, MmLeafDownArgs)
+HX_ONE_LAUNCHER(sw_root_mm, SwRootArgs)
+#undef HX_ONE_LAUNCHER
+
 #define HX_INST(T)                                                                                     \
-  template size_t leaf_up_lds_bytes<T>(int, int);                                                      \
+  template size_t leaf_up_lds_bytes<T>(int, int, bool);                                                      \
   template hipError_t launch_leaf_up_mm_multi<T>(const Multi<MmLeafUpArgs<T>>&, int, int, size_t, hipStream_t); \
   template hipError_t launch_merge_up_mm_multi<T>(const Multi<MmMergeArgs<T>>&, int, int, hipStream_t);   \
   template hipError_t launch_merge_down_mm_multi<T>(const Multi<MmMergeArgs<T>>&, int, int, hipStream_t); \
   template hipError_t launch_leaf_down_mm_multi<T>(const Multi<MmLeafDownArgs<T>>&, int, int, hipStream_t); \
   template hipError_t launch_leaf_down_sum_mm_multi<T>(const Multi<MmLeafDownArgs<T>>&, int, int, hipStream_t); \
-  template hipError_t launch_sw_root_mm_multi<T>(const Multi<SwRootArgs<T>>&, int, int, hipStream_t);
+  template hipError_t launch_sw_root_mm_multi<T>(const Multi<SwRootArgs<T>>&, int, int, hipStream_t);   \
+  template hipError_t launch_leaf_up_mm_one<T>(const MmLeafUpArgs<T>&, int, int, size_t, hipStream_t);    \
+  template hipError_t launch_merge_up_mm_one<T>(const MmMergeArgs<T>&, int, int, hipStream_t);            \
+  template hipError_t launch_merge_down_mm_one<T>(const MmMergeArgs<T>&, int, int, hipStream_t);          \
+  template hipError_t launch_leaf_down_mm_one<T>(const MmLeafDownArgs<T>&, int, int, hipStream_t);        \
+  template hipError_t launch_leaf_down_sum_mm_one<T>(const MmLeafDownArgs<T>&, int, int, hipStream_t);    \
+  template hipError_t launch_sw_root_mm_one<T>(const SwRootArgs<T>&, int, int, hipStream_t);
 HX_INST(float)
 HX_INST(double)
 #undef HX_INST

@@ -121,6 +121,7 @@ struct MmLeafUpArgs {
   // precision form, correction sweep: right-hand side taken from the
   // residual [pole][leaf][q*q][rhs] instead of the state (null: state)
   const typename Cplx<T>::type* gin;
+  int w_lds;                 // keep the w tile in LDS for h (the launch's LDS allows it)
 };
 
 template <class T>
@@ -287,9 +288,21 @@ template <class T> hipError_t launch_merge_down_mm_multi(const Multi<MmMergeArgs
 template <class T> hipError_t launch_leaf_down_mm_multi(const Multi<MmLeafDownArgs<T>>& m, int blocks, int nt, hipStream_t s);
 template <class T> hipError_t launch_leaf_down_sum_mm_multi(const Multi<MmLeafDownArgs<T>>& m, int blocks, int nt, hipStream_t s);
 template <class T> hipError_t launch_sw_root_mm_multi(const Multi<SwRootArgs<T>>& m, int blocks, int nt, hipStream_t s);
+// The same launches for one instance, arguments by value.
+template <class T> hipError_t launch_leaf_up_mm_one(const MmLeafUpArgs<T>& a, int blocks, int nt, size_t lds, hipStream_t s);
+template <class T> hipError_t launch_merge_up_mm_one(const MmMergeArgs<T>& a, int blocks, int nt, hipStream_t s);
+template <class T> hipError_t launch_merge_down_mm_one(const MmMergeArgs<T>& a, int blocks, int nt, hipStream_t s);
+template <class T> hipError_t launch_leaf_down_mm_one(const MmLeafDownArgs<T>& a, int blocks, int nt, hipStream_t s);
+template <class T> hipError_t launch_leaf_down_sum_mm_one(const MmLeafDownArgs<T>& a, int blocks, int nt, hipStream_t s);
+template <class T> hipError_t launch_sw_root_mm_one(const SwRootArgs<T>& a, int blocks, int nt, hipStream_t s);
+hipError_t launch_residual_one(const ResidualArgs& a, int blocks, bool sw, size_t lds, hipStream_t s);
+hipError_t launch_sw_prep_one(const SwPrepArgs& a, int blocks, hipStream_t s);
+hipError_t launch_sw_wall_one(const SwWallArgs& a, int blocks, hipStream_t s);
+template <class T>
+hipError_t launch_sw_post_one(const SwPostArgs<T>& a, int blocks, size_t lds, hipStream_t s);
 // LDS bytes of the leaf upward kernel (above 64 KiB the launcher raises the
 // kernel's dynamic LDS limit).
-template <class T> size_t leaf_up_lds_bytes(int q, int nt);
+template <class T> size_t leaf_up_lds_bytes(int q, int nt, bool with_w);
 
 // nt = right-hand-side tiles of 16 per block (1 or 2)
 template <class T> hipError_t launch_leaf_up_mm(const MmLeafUpArgs<T>& a, int n_leaf, int nt, hipStream_t s);

@@ -1286,10 +1286,12 @@ void record_instance(const hx_plan* plan, const Instance& I, int inst, double* s
     lu.h = vec(I.levels[0].d_h);
     lu.h_pole = I.levels[0].total_ext;
     lu.gin = pass ? gres : nullptr;
-    // two tiles only while the staged right-hand sides fit in 64 KiB of LDS
+    // two tiles only while the staged right-hand sides fit in 64 KiB of LDS;
+    // the w tile joins them in LDS when the total stays within 64 KiB
     int nt = stage_nt(I, O_LEAF_UP);
-    if (nt == 2 && hx::leaf_up_lds_bytes<T>(I.q, 2) > 65536) nt = 1;
-    const size_t lds = hx::leaf_up_lds_bytes<T>(I.q, nt);
+    if (nt == 2 && hx::leaf_up_lds_bytes<T>(I.q, 2, false) > 65536) nt = 1;
+    lu.w_lds = hx::leaf_up_lds_bytes<T>(I.q, nt, true) <= 65536 ? 1 : 0;
+    const size_t lds = hx::leaf_up_lds_bytes<T>(I.q, nt, lu.w_lds != 0);
     R.add(pass, O_LEAF_UP, 0, dbl ? K_LU_D : K_LU_F, nt,
           (long long)I.n_leaf * I.npole * hx::mm_tiles(I.nrhs, nt), lds, lu, HX_K_LEAF_UP, inst);
 
@@ -1528,7 +1530,40 @@ hx::Multi<A> multi_of(const hx_plan* plan, const Group& g) {
   return m;
 }
 
-hipError_t launch_group(const hx_plan* plan, const Group& g, hipStream_t s) {
+template <class A>
+const A& host_args(const unsigned char* blob, const Group& g) {
+  return *reinterpret_cast<const A*>(blob + g.args_off);
+}
+
+// A group of one instance: the single-instance kernel, arguments by value.
+hipError_t launch_one(const unsigned char* blob, const Group& g, hipStream_t s) {
+  const int b = (int)g.blocks;
+  switch (g.kind) {
+    case K_LU_D: return hx::launch_leaf_up_mm_one<double>(host_args<hx::MmLeafUpArgs<double>>(blob, g), b, g.nt, g.lds, s);
+    case K_LU_F: return hx::launch_leaf_up_mm_one<float>(host_args<hx::MmLeafUpArgs<float>>(blob, g), b, g.nt, g.lds, s);
+    case K_MU_D: return hx::launch_merge_up_mm_one<double>(host_args<hx::MmMergeArgs<double>>(blob, g), b, g.nt, s);
+    case K_MU_F: return hx::launch_merge_up_mm_one<float>(host_args<hx::MmMergeArgs<float>>(blob, g), b, g.nt, s);
+    case K_MD_D: return hx::launch_merge_down_mm_one<double>(host_args<hx::MmMergeArgs<double>>(blob, g), b, g.nt, s);
+    case K_MD_F: return hx::launch_merge_down_mm_one<float>(host_args<hx::MmMergeArgs<float>>(blob, g), b, g.nt, s);
+    case K_LD_D: return hx::launch_leaf_down_mm_one<double>(host_args<hx::MmLeafDownArgs<double>>(blob, g), b, g.nt, s);
+    case K_LD_F: return hx::launch_leaf_down_mm_one<float>(host_args<hx::MmLeafDownArgs<float>>(blob, g), b, g.nt, s);
+    case K_LDS_D: return hx::launch_leaf_down_sum_mm_one<double>(host_args<hx::MmLeafDownArgs<double>>(blob, g), b, g.nt, s);
+    case K_LDS_F: return hx::launch_leaf_down_sum_mm_one<float>(host_args<hx::MmLeafDownArgs<float>>(blob, g), b, g.nt, s);
+    case K_ROOT_D: return hx::launch_sw_root_mm_one<double>(host_args<hx::SwRootArgs<double>>(blob, g), b, g.nt, s);
+    case K_ROOT_F: return hx::launch_sw_root_mm_one<float>(host_args<hx::SwRootArgs<float>>(blob, g), b, g.nt, s);
+    case K_RES_W: return hx::launch_residual_one(host_args<hx::ResidualArgs>(blob, g), b, false, g.lds, s);
+    case K_RES_S: return hx::launch_residual_one(host_args<hx::ResidualArgs>(blob, g), b, true, g.lds, s);
+    case K_PREP: return hx::launch_sw_prep_one(host_args<hx::SwPrepArgs>(blob, g), b, s);
+    case K_WALL: return hx::launch_sw_wall_one(host_args<hx::SwWallArgs>(blob, g), b, s);
+    case K_POST_D: return hx::launch_sw_post_one<double>(host_args<hx::SwPostArgs<double>>(blob, g), b, g.lds, s);
+    case K_POST_F: return hx::launch_sw_post_one<float>(host_args<hx::SwPostArgs<float>>(blob, g), b, g.lds, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// blob: the host copy of the tables the group was packed into.
+hipError_t launch_group(const hx_plan* plan, const Group& g, const unsigned char* blob, hipStream_t s) {
+  if (g.n == 1) return launch_one(blob, g, s);
   const int b = (int)g.blocks;
   switch (g.kind) {
     case K_LU_D: return hx::launch_leaf_up_mm_multi<double>(multi_of<hx::MmLeafUpArgs<double>>(plan, g), b, g.nt, g.lds, s);
@@ -1609,7 +1644,7 @@ hx_status tune_instance(hx_plan* plan, Instance& I, int k, double* scratch, hipS
       float t_min = 1e30f;
       for (int rep = 0; rep < 4; ++rep) {   // the first run warms up
         HIP_OK(hipEventRecord(e0, s));
-        for (const Group& g : groups) HIP_OK(launch_group(plan, g, s));
+        for (const Group& g : groups) HIP_OK(launch_group(plan, g, blob.data(), s));
         HIP_OK(hipEventRecord(e1, s));
         HIP_OK(hipEventSynchronize(e1));
         float ms = 0.0f;
@@ -1755,7 +1790,7 @@ hx_status enqueue_step(hx_plan* plan, double* const* states, hipStream_t s, Prof
     ps.inv_tau = 1.0 / I.tau;
     TIMED(HX_K_POLE_SUM, hx::launch_pole_sum(ps, I.n_leaf, s));
   }
-  for (const Group& g : plan->groups) TIMED(g.cls, launch_group(plan, g, s));
+  for (const Group& g : plan->groups) TIMED(g.cls, launch_group(plan, g, plan->tab_blob.data(), s));
   return HX_OK;
 }
 

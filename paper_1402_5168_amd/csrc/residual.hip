@@ -305,6 +305,15 @@ hipError_t launch_residual(const ResidualArgs& a0, int n_leaf, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_residual_one(const ResidualArgs& a, int blocks, bool sw, size_t lds, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  const hipError_t e = sw ? allow_residual_lds<true>(lds, false) : allow_residual_lds<false>(lds, false);
+  if (e != hipSuccess) return e;
+  if (sw) hipLaunchKernelGGL(k_residual<true>, dim3(blocks), dim3(kBlock), lds, s, a);
+  else hipLaunchKernelGGL(k_residual<false>, dim3(blocks), dim3(kBlock), lds, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_residual_multi(const Multi<ResidualArgs>& m, int blocks, bool sw, size_t lds,
                                  hipStream_t s) {
   if (blocks <= 0) return hipSuccess;

@@ -292,6 +292,27 @@ hipError_t launch_sw_post_multi(const Multi<SwPostArgs<T>>& m, int blocks, size_
   return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_sw_post_one(const SwPostArgs<T>& a, int blocks, size_t lds, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_sw_post<T>), dim3(blocks), dim3(kBlock), lds, s, a);
+  return hipGetLastError();
+}
+template hipError_t launch_sw_post_one<double>(const SwPostArgs<double>&, int, size_t, hipStream_t);
+template hipError_t launch_sw_post_one<float>(const SwPostArgs<float>&, int, size_t, hipStream_t);
+
+hipError_t launch_sw_prep_one(const SwPrepArgs& a, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sw_prep, dim3(blocks), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sw_wall_one(const SwWallArgs& a, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sw_wall, dim3(blocks), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_sw_prep_multi(const Multi<SwPrepArgs>& m, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_sw_prep_multi, dim3(blocks), dim3(kBlock), 0, s, m);
