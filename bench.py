@@ -38,6 +38,31 @@ FP64_PEAK_TFLOPS = 78.6       # MI355X dense FP64 (vector and matrix)
 FP32_PEAK_TFLOPS = 157.3      # MI355X dense FP32 (vector and matrix)
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_wave_64x64_p10_fp32refine_r32.md")
+TRAFFIC_SOURCES = ("apply_mm.hip", "hx_kernels.h", "hx_internal.h")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch (read + written) of `kernel` from the committed
+    counter record of the default workload, or None when the record is
+    missing, is for another kernel, or the kernel sources changed since."""
+    import hashlib
+    import re
+
+    if not os.path.exists(TRAFFIC_RECORD):
+        return None
+    m = re.search(r'traffic-record kernel="([^"]+)" fetch_bytes=(\d+) write_bytes=(\d+) '
+                  r'sources_sha256=([0-9a-f]+)', open(TRAFFIC_RECORD).read())
+    if not m or m.group(1) != kernel:
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1402_5168_amd", "csrc", f), "rb").read())
+    if h.hexdigest() != m.group(4):
+        return None
+    return {"read": int(m.group(2)), "written": int(m.group(3))}
+
+
 def interface_nodes(mesh, walls: bool = False) -> int:
     """Sum over elements of their edge nodes that are unknowns (interfaces;
     with slip walls also the wall nodes)."""
@@ -230,9 +255,12 @@ def run(w, precision: str, unbatched: bool, steps: int, warmup: int, profile: bo
             dom["flops_per_launch"] = flops
             dom["TFLOPs"] = tf
             peak = FP32_PEAK_TFLOPS if fp32 else FP64_PEAK_TFLOPS
+            tr = measured_traffic("hx::k_leaf_up_mm<float, 2>") if (
+                fp32 and not sw and w.recipe.name == "wave_64x64_p10" and nrhs == 32) else None
             out["roofline"] = {"bound": "mfma", "kernel": "k_leaf_up", "achieved": tf,
                                "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
-                               "traffic": None,
+                               "traffic": None if tr is None else tr["read"] + tr["written"],
+                               "traffic_split": tr,
                                "step_TFLOPs": info["flops_per_step"] / (ms_step * 1e-3) / 1e12}
         else:
             out["roofline"] = {"bound": "hbm", "kernel": "k_leaf_up", "achieved": dom["GBps"],
