@@ -98,9 +98,11 @@ typedef enum {
                                        batching them on the matrix cores
                                        (reference for the batching speedup)  */
 #define HX_FLAG_AUTOTUNE       0x10u /* hx_plan_build times each batched
-                                        instance's stages with one and two
-                                        right-hand-side tiles per block and
-                                        keeps the faster (hx_plan_tiles)     */
+                                        instance's stages in each candidate
+                                        shape (one or two right-hand-side
+                                        tiles per block; merges also one-wave
+                                        blocks) and keeps the fastest
+                                        (hx_plan_tiles)                      */
 
 /* Mesh: [x0,x1] x [y0,y1] split into nex x ney equal elements, each with a
  * p x p Chebyshev-Lobatto grid (section 2.2).  nex and ney are powers of

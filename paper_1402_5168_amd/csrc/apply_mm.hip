@@ -271,11 +271,12 @@ __global__ __launch_bounds__(kBlock) void k_leaf_up_mm_multi(Multi<MmLeafUpArgs<
 
 // ---- merge upward: g3 = h3a + h3b (- j3), h_par = [h1a; h2b] - Y g3 ----------
 // block = (box, pole, rhs tile, row group of 64 rows of Y)
-template <class T, int NT>
+template <class T, int NT, int WV>
 __device__ __forceinline__ void merge_up_body(const MmMergeArgs<T>& a, const int bid) {
   using C = typename MM<T>::C;
   constexpr int RT = 16 * NT, BST = RT + 1;
-  __shared__ C Bs[kKC * BST];
+  constexpr int RB = 16 * WV, KC = WV == 4 ? kKC : 32;  // rows per block, k-chunk
+  __shared__ C Bs[KC * BST];
   const int n_rt = (a.nrhs + RT - 1) / RT;
   int rest = bid;
   const int rg = rest % a.row_groups; rest /= a.row_groups;
@@ -284,7 +285,7 @@ __device__ __forceinline__ void merge_up_body(const MmMergeArgs<T>& a, const int
   const int box = rest / a.npole;
   const BoxDesc B = a.boxes[box];
   const int n1 = B.n1, n2 = B.n2, n3 = B.n3, ext = n1 + n2;
-  if (rg > 0 && rg * 64 >= ext) return;
+  if (rg > 0 && rg * RB >= ext) return;
   const int* i1 = a.idx + B.idx_off;
   const int* i2 = i1 + n1;
   const int* i3a = i2 + n2;
@@ -293,11 +294,11 @@ __device__ __forceinline__ void merge_up_body(const MmMergeArgs<T>& a, const int
   const C* hc = a.child + (long long)pole * a.child_pole * r;
   C* g3 = a.g3 + ((long long)pole * a.g3_pole + B.g3_off) * r;
   const C* Y = a.ops + pole * a.pole_stride + B.op_off + (long long)n3 * (ext + n3);
-  const int row0 = rg * 64 + (threadIdx.x >> 6) * 16;
+  const int row0 = rg * RB + (threadIdx.x >> 6) * 16;
   Acc<T, NT> acc;
   acc.zero();
-  for (int k0 = 0; k0 < n3; k0 += kKC) {
-    const int kc = min(kKC, n3 - k0), kcp = (kc + 3) & ~3;
+  for (int k0 = 0; k0 < n3; k0 += KC) {
+    const int kc = min(KC, n3 - k0), kcp = (kc + 3) & ~3;
     for (int idx = threadIdx.x; idx < kcp * RT; idx += blockDim.x) {
       const int k = idx / RT, j = idx - k * RT;
       const int rhs = rt * RT + j;
@@ -340,25 +341,26 @@ __device__ __forceinline__ void merge_up_body(const MmMergeArgs<T>& a, const int
   });
 }
 
-template <class T, int NT>
-__global__ __launch_bounds__(kBlock) void k_merge_up_mm(MmMergeArgs<T> a) {
-  merge_up_body<T, NT>(a, blockIdx.x);
+template <class T, int NT, int WV = 4>
+__global__ __launch_bounds__(64 * WV) void k_merge_up_mm(MmMergeArgs<T> a) {
+  merge_up_body<T, NT, WV>(a, blockIdx.x);
 }
 
-template <class T, int NT>
-__global__ __launch_bounds__(kBlock) void k_merge_up_mm_multi(Multi<MmMergeArgs<T>> m) {
+template <class T, int NT, int WV = 4>
+__global__ __launch_bounds__(64 * WV) void k_merge_up_mm_multi(Multi<MmMergeArgs<T>> m) {
   int i;
   const int bid = m.locate(blockIdx.x, i);
   const MmMergeArgs<T> a = m.args[i];
-  merge_up_body<T, NT>(a, bid);
+  merge_up_body<T, NT, WV>(a, bid);
 }
 
 // ---- merge downward: u3 = -Z [u_ext; g3], scattered to the children --------
-template <class T, int NT>
+template <class T, int NT, int WV>
 __device__ __forceinline__ void merge_down_body(const MmMergeArgs<T>& a, const int bid) {
   using C = typename MM<T>::C;
   constexpr int RT = 16 * NT, BST = RT + 1;
-  __shared__ C Bs[kKC * BST];
+  constexpr int RB = 16 * WV, KC = WV == 4 ? kKC : 32;  // rows per block, k-chunk
+  __shared__ C Bs[KC * BST];
   const int n_rt = (a.nrhs + RT - 1) / RT;
   int rest = bid;
   const int rg = rest % a.row_groups; rest /= a.row_groups;
@@ -367,7 +369,7 @@ __device__ __forceinline__ void merge_down_body(const MmMergeArgs<T>& a, const i
   const int box = rest / a.npole;
   const BoxDesc B = a.boxes[box];
   const int n1 = B.n1, n2 = B.n2, n3 = B.n3, ext = n1 + n2, m = ext + n3;
-  if (rg * 64 >= n3) return;
+  if (rg * RB >= n3) return;
   const int* i1 = a.idx + B.idx_off;
   const int* i2 = i1 + n1;
   const int* i3a = i2 + n2;
@@ -387,11 +389,11 @@ __device__ __forceinline__ void merge_down_body(const MmMergeArgs<T>& a, const i
     }
   }
   const C* Z = a.ops + pole * a.pole_stride + B.op_off;
-  const int row0 = rg * 64 + (threadIdx.x >> 6) * 16;
+  const int row0 = rg * RB + (threadIdx.x >> 6) * 16;
   Acc<T, NT> acc;
   acc.zero();
-  for (int k0 = 0; k0 < m; k0 += kKC) {
-    const int kc = min(kKC, m - k0), kcp = (kc + 3) & ~3;
+  for (int k0 = 0; k0 < m; k0 += KC) {
+    const int kc = min(KC, m - k0), kcp = (kc + 3) & ~3;
     for (int idx = threadIdx.x; idx < kcp * RT; idx += blockDim.x) {
       const int k = idx / RT, j = idx - k * RT;
       const int rhs = rt * RT + j;
@@ -419,17 +421,17 @@ __device__ __forceinline__ void merge_down_body(const MmMergeArgs<T>& a, const i
   });
 }
 
-template <class T, int NT>
-__global__ __launch_bounds__(kBlock) void k_merge_down_mm(MmMergeArgs<T> a) {
-  merge_down_body<T, NT>(a, blockIdx.x);
+template <class T, int NT, int WV = 4>
+__global__ __launch_bounds__(64 * WV) void k_merge_down_mm(MmMergeArgs<T> a) {
+  merge_down_body<T, NT, WV>(a, blockIdx.x);
 }
 
-template <class T, int NT>
-__global__ __launch_bounds__(kBlock) void k_merge_down_mm_multi(Multi<MmMergeArgs<T>> m) {
+template <class T, int NT, int WV = 4>
+__global__ __launch_bounds__(64 * WV) void k_merge_down_mm_multi(Multi<MmMergeArgs<T>> m) {
   int i;
   const int bid = m.locate(blockIdx.x, i);
   const MmMergeArgs<T> a = m.args[i];
-  merge_down_body<T, NT>(a, bid);
+  merge_down_body<T, NT, WV>(a, bid);
 }
 
 // ---- leaf downward: y = w - S u_e (in place of w) -----------------------------
@@ -775,8 +777,6 @@ hipError_t launch_leaf_up_mm_multi(const Multi<MmLeafUpArgs<T>>& m, int blocks, 
     else hipLaunchKernelGGL((k_##NAME##_multi<T, 1>), dim3(blocks), dim3(kBlock), 0, s, m);   \
     return hipGetLastError();                                                                  \
   }
-HX_MULTI_LAUNCHER(merge_up_mm, MmMergeArgs)
-HX_MULTI_LAUNCHER(merge_down_mm, MmMergeArgs)
 HX_MULTI_LAUNCHER(leaf_down_mm, MmLeafDownArgs)
 HX_MULTI_LAUNCHER(leaf_down_sum_mm, MmLeafDownArgs)
 HX_MULTI_LAUNCHER(sw_root_mm, SwRootArgs)
@@ -807,24 +807,53 @@ hipError_t launch_leaf_up_mm_one(const MmLeafUpArgs<T>& a, int blocks, int nt, s
     else hipLaunchKernelGGL((k_##NAME<T, 1>), dim3(blocks), dim3(kBlock), 0, s, a);           \
     return hipGetLastError();                                                                  \
   }
-HX_ONE_LAUNCHER(merge_up_mm, MmMergeArgs)
-HX_ONE_LAUNCHER(merge_down_mm, MmMergeArgs)
 HX_ONE_LAUNCHER(leaf_down_mm, MmLeafDownArgs)
 HX_ONE_LAUNCHER(leaf_down_sum_mm, MmLeafDownArgs)
 HX_ONE_LAUNCHER(sw_root_mm, SwRootArgs)
 #undef HX_ONE_LAUNCHER
 
+// Merge launches: wv waves per block (4: 64 rows per block, 1: 16 rows).
+#define HX_MERGE_LAUNCHERS(NAME)                                                                   \
+  template <class T>                                                                               \
+  hipError_t launch_##NAME##_multi(const Multi<MmMergeArgs<T>>& m, int blocks, int nt, int wv,     \
+                                   hipStream_t s) {                                                \
+    if (blocks <= 0) return hipSuccess;                                                            \
+    if (wv == 1) {                                                                                 \
+      if (nt == 2) hipLaunchKernelGGL((k_##NAME##_multi<T, 2, 1>), dim3(blocks), dim3(64), 0, s, m); \
+      else hipLaunchKernelGGL((k_##NAME##_multi<T, 1, 1>), dim3(blocks), dim3(64), 0, s, m);       \
+    } else {                                                                                       \
+      if (nt == 2) hipLaunchKernelGGL((k_##NAME##_multi<T, 2, 4>), dim3(blocks), dim3(kBlock), 0, s, m); \
+      else hipLaunchKernelGGL((k_##NAME##_multi<T, 1, 4>), dim3(blocks), dim3(kBlock), 0, s, m);   \
+    }                                                                                              \
+    return hipGetLastError();                                                                      \
+  }                                                                                                \
+  template <class T>                                                                               \
+  hipError_t launch_##NAME##_one(const MmMergeArgs<T>& a, int blocks, int nt, int wv, hipStream_t s) { \
+    if (blocks <= 0) return hipSuccess;                                                            \
+    if (wv == 1) {                                                                                 \
+      if (nt == 2) hipLaunchKernelGGL((k_##NAME<T, 2, 1>), dim3(blocks), dim3(64), 0, s, a);       \
+      else hipLaunchKernelGGL((k_##NAME<T, 1, 1>), dim3(blocks), dim3(64), 0, s, a);               \
+    } else {                                                                                       \
+      if (nt == 2) hipLaunchKernelGGL((k_##NAME<T, 2, 4>), dim3(blocks), dim3(kBlock), 0, s, a);   \
+      else hipLaunchKernelGGL((k_##NAME<T, 1, 4>), dim3(blocks), dim3(kBlock), 0, s, a);           \
+    }                                                                                              \
+    return hipGetLastError();                                                                      \
+  }
+HX_MERGE_LAUNCHERS(merge_up_mm)
+HX_MERGE_LAUNCHERS(merge_down_mm)
+#undef HX_MERGE_LAUNCHERS
+
 #define HX_INST(T)                                                                                     \
   template size_t leaf_up_lds_bytes<T>(int, int, bool);                                                      \
   template hipError_t launch_leaf_up_mm_multi<T>(const Multi<MmLeafUpArgs<T>>&, int, int, size_t, hipStream_t); \
-  template hipError_t launch_merge_up_mm_multi<T>(const Multi<MmMergeArgs<T>>&, int, int, hipStream_t);   \
-  template hipError_t launch_merge_down_mm_multi<T>(const Multi<MmMergeArgs<T>>&, int, int, hipStream_t); \
+  template hipError_t launch_merge_up_mm_multi<T>(const Multi<MmMergeArgs<T>>&, int, int, int, hipStream_t);   \
+  template hipError_t launch_merge_down_mm_multi<T>(const Multi<MmMergeArgs<T>>&, int, int, int, hipStream_t); \
   template hipError_t launch_leaf_down_mm_multi<T>(const Multi<MmLeafDownArgs<T>>&, int, int, hipStream_t); \
   template hipError_t launch_leaf_down_sum_mm_multi<T>(const Multi<MmLeafDownArgs<T>>&, int, int, hipStream_t); \
   template hipError_t launch_sw_root_mm_multi<T>(const Multi<SwRootArgs<T>>&, int, int, hipStream_t);   \
   template hipError_t launch_leaf_up_mm_one<T>(const MmLeafUpArgs<T>&, int, int, size_t, hipStream_t);    \
-  template hipError_t launch_merge_up_mm_one<T>(const MmMergeArgs<T>&, int, int, hipStream_t);            \
-  template hipError_t launch_merge_down_mm_one<T>(const MmMergeArgs<T>&, int, int, hipStream_t);          \
+  template hipError_t launch_merge_up_mm_one<T>(const MmMergeArgs<T>&, int, int, int, hipStream_t);            \
+  template hipError_t launch_merge_down_mm_one<T>(const MmMergeArgs<T>&, int, int, int, hipStream_t);          \
   template hipError_t launch_leaf_down_mm_one<T>(const MmLeafDownArgs<T>&, int, int, hipStream_t);        \
   template hipError_t launch_leaf_down_sum_mm_one<T>(const MmLeafDownArgs<T>&, int, int, hipStream_t);    \
   template hipError_t launch_sw_root_mm_one<T>(const SwRootArgs<T>&, int, int, hipStream_t);

@@ -283,15 +283,15 @@ hipError_t launch_residual_multi(const Multi<ResidualArgs>& m, int blocks, bool 
 // Multi-instance variants: one launch over the blocks of every instance in
 // the table, all with the same tile count nt (1 or 2) and LDS bytes.
 template <class T> hipError_t launch_leaf_up_mm_multi(const Multi<MmLeafUpArgs<T>>& m, int blocks, int nt, size_t lds, hipStream_t s);
-template <class T> hipError_t launch_merge_up_mm_multi(const Multi<MmMergeArgs<T>>& m, int blocks, int nt, hipStream_t s);
-template <class T> hipError_t launch_merge_down_mm_multi(const Multi<MmMergeArgs<T>>& m, int blocks, int nt, hipStream_t s);
+template <class T> hipError_t launch_merge_up_mm_multi(const Multi<MmMergeArgs<T>>& m, int blocks, int nt, int wv, hipStream_t s);
+template <class T> hipError_t launch_merge_down_mm_multi(const Multi<MmMergeArgs<T>>& m, int blocks, int nt, int wv, hipStream_t s);
 template <class T> hipError_t launch_leaf_down_mm_multi(const Multi<MmLeafDownArgs<T>>& m, int blocks, int nt, hipStream_t s);
 template <class T> hipError_t launch_leaf_down_sum_mm_multi(const Multi<MmLeafDownArgs<T>>& m, int blocks, int nt, hipStream_t s);
 template <class T> hipError_t launch_sw_root_mm_multi(const Multi<SwRootArgs<T>>& m, int blocks, int nt, hipStream_t s);
 // The same launches for one instance, arguments by value.
 template <class T> hipError_t launch_leaf_up_mm_one(const MmLeafUpArgs<T>& a, int blocks, int nt, size_t lds, hipStream_t s);
-template <class T> hipError_t launch_merge_up_mm_one(const MmMergeArgs<T>& a, int blocks, int nt, hipStream_t s);
-template <class T> hipError_t launch_merge_down_mm_one(const MmMergeArgs<T>& a, int blocks, int nt, hipStream_t s);
+template <class T> hipError_t launch_merge_up_mm_one(const MmMergeArgs<T>& a, int blocks, int nt, int wv, hipStream_t s);
+template <class T> hipError_t launch_merge_down_mm_one(const MmMergeArgs<T>& a, int blocks, int nt, int wv, hipStream_t s);
 template <class T> hipError_t launch_leaf_down_mm_one(const MmLeafDownArgs<T>& a, int blocks, int nt, hipStream_t s);
 template <class T> hipError_t launch_leaf_down_sum_mm_one(const MmLeafDownArgs<T>& a, int blocks, int nt, hipStream_t s);
 template <class T> hipError_t launch_sw_root_mm_one(const SwRootArgs<T>& a, int blocks, int nt, hipStream_t s);

@@ -110,6 +110,7 @@ struct Instance {
   long long leaf_ops = 0, merge_ops = 0;    // complex elements per pole
   double max_abs_R = 0.0, fit_X = 0.0, sum_abs_b = 0.0;
   int tune_nt[8] = {0, 0, 0, 0, 0, 0, 0, 0}; // per stage: right-hand-side tiles (0: default)
+  int tune_wv[8] = {0, 0, 0, 0, 0, 0, 0, 0}; // merge stages: 1 = one-wave blocks at every level
   bool fp32 = false;                        // precision form: FP32 operators and sweeps
   // shallow water: wall nodes are exterior unknowns up to the root
   bool sw = false;
@@ -134,7 +135,7 @@ struct Instance {
 // One fused launch of the batched instances: a stage kind and tile count,
 // its instances' argument table and block offsets inside the arena.
 struct Group {
-  int kind, nt, cls, n;
+  int kind, nt, wv, cls, n;
   long long blocks;
   size_t lds, args_off, first_off;
 };
@@ -1171,7 +1172,7 @@ enum StageOrder : int { O_PREP, O_LEAF_UP, O_MERGE_UP, O_ROOT, O_MERGE_DOWN, O_L
 
 
 struct Rec {
-  int pass, order, level, kind, nt, cls, inst;
+  int pass, order, level, kind, nt, wv, cls, inst;
   long long blocks;
   size_t lds, args_size;
   unsigned char args[kArgsMax];
@@ -1181,7 +1182,7 @@ struct Recorder {
   std::vector<Rec> recs;
   template <class A>
   void add(int pass, int order, int level, int kind, int nt, long long blocks, size_t lds,
-           const A& a, int cls, int inst) {
+           const A& a, int cls, int inst, int wv = 4) {
     static_assert(sizeof(A) <= kArgsMax, "argument block too large");
     Rec r;
     r.pass = pass;
@@ -1189,6 +1190,7 @@ struct Recorder {
     r.level = level;
     r.kind = kind;
     r.nt = nt;
+    r.wv = wv;
     r.cls = cls;
     r.inst = inst;
     r.blocks = blocks;
@@ -1205,6 +1207,14 @@ int stage_nt(const Instance& I, int order) {
   const int t = I.tune_nt[order];
   if (t == 1 || (t == 2 && I.nrhs > 16)) return t;
   return I.nrhs > 16 ? 2 : 1;
+}
+
+// Waves per block of a merge level with `rows` output rows: one wave (16
+// rows per block) when the level's rows fit one 16-row tile, or when the
+// tuned choice says so; four waves (64 rows per block) otherwise.
+int merge_wv(const Instance& I, int order, int rows) {
+  if (I.tune_wv[order] == 1) return 1;
+  return rows <= 16 ? 1 : 4;
 }
 
 template <class T>
@@ -1304,7 +1314,8 @@ void record_instance(const hx_plan* plan, const Instance& I, int inst, double* s
       m.idx = idx;
       m.npole = I.npole;
       m.nrhs = I.nrhs;
-      m.row_groups = std::max(1, (L.max_ext + 63) / 64);
+      const int wv = merge_wv(I, O_MERGE_UP, L.max_ext);
+      m.row_groups = std::max(1, (L.max_ext + 16 * wv - 1) / (16 * wv));
       m.child = vec(I.levels[l - 1].d_h);
       m.child_pole = I.levels[l - 1].total_ext;
       m.self = vec(L.d_h);
@@ -1316,7 +1327,7 @@ void record_instance(const hx_plan* plan, const Instance& I, int inst, double* s
       const int mnt = stage_nt(I, O_MERGE_UP);
       R.add(pass, O_MERGE_UP, (int)l, dbl ? K_MU_D : K_MU_F, mnt,
             (long long)L.boxes.size() * I.npole * hx::mm_tiles(I.nrhs, mnt) * m.row_groups, 0, m,
-            HX_K_MERGE_UP, inst);
+            HX_K_MERGE_UP, inst, wv);
     }
     if (sw) {
       const Level& Rt = I.levels[nl - 1];
@@ -1351,7 +1362,8 @@ void record_instance(const hx_plan* plan, const Instance& I, int inst, double* s
       m.idx = idx;
       m.npole = I.npole;
       m.nrhs = I.nrhs;
-      m.row_groups = std::max(1, (L.max_n3 + 63) / 64);
+      const int wv = merge_wv(I, O_MERGE_DOWN, L.max_n3);
+      m.row_groups = std::max(1, (L.max_n3 + 16 * wv - 1) / (16 * wv));
       m.child = vec(I.levels[l - 1].d_u);
       m.child_pole = I.levels[l - 1].total_ext;
       m.self = vec(L.d_u);
@@ -1361,7 +1373,7 @@ void record_instance(const hx_plan* plan, const Instance& I, int inst, double* s
       const int mnt = stage_nt(I, O_MERGE_DOWN);
       R.add(pass, O_MERGE_DOWN, -(int)l, dbl ? K_MD_D : K_MD_F, mnt,
             (long long)L.boxes.size() * I.npole * hx::mm_tiles(I.nrhs, mnt) * m.row_groups, 0, m,
-            HX_K_MERGE_DOWN, inst);
+            HX_K_MERGE_DOWN, inst, wv);
     }
     hx::MmLeafDownArgs<T> ld{};
     ld.ops = ops;
@@ -1484,7 +1496,8 @@ void group_stages(Recorder& R, std::vector<Group>& groups, std::vector<unsigned 
     if (x.order != y.order) return x.order < y.order;
     if (x.level != y.level) return x.level < y.level;
     if (x.kind != y.kind) return x.kind < y.kind;
-    return x.nt < y.nt;
+    if (x.nt != y.nt) return x.nt < y.nt;
+    return x.wv < y.wv;
   });
   groups.clear();
   blob.clear();
@@ -1493,11 +1506,13 @@ void group_stages(Recorder& R, std::vector<Group>& groups, std::vector<unsigned 
     size_t j = i;
     const Rec& h = R.recs[i];
     while (j < R.recs.size() && R.recs[j].pass == h.pass && R.recs[j].order == h.order &&
-           R.recs[j].level == h.level && R.recs[j].kind == h.kind && R.recs[j].nt == h.nt)
+           R.recs[j].level == h.level && R.recs[j].kind == h.kind && R.recs[j].nt == h.nt &&
+           R.recs[j].wv == h.wv)
       ++j;
     Group g{};
     g.kind = h.kind;
     g.nt = h.nt;
+    g.wv = h.wv;
     g.cls = h.cls;
     g.n = (int)(j - i);
     g.args_off = align_up(blob.size());
@@ -1541,10 +1556,10 @@ hipError_t launch_one(const unsigned char* blob, const Group& g, hipStream_t s) 
   switch (g.kind) {
     case K_LU_D: return hx::launch_leaf_up_mm_one<double>(host_args<hx::MmLeafUpArgs<double>>(blob, g), b, g.nt, g.lds, s);
     case K_LU_F: return hx::launch_leaf_up_mm_one<float>(host_args<hx::MmLeafUpArgs<float>>(blob, g), b, g.nt, g.lds, s);
-    case K_MU_D: return hx::launch_merge_up_mm_one<double>(host_args<hx::MmMergeArgs<double>>(blob, g), b, g.nt, s);
-    case K_MU_F: return hx::launch_merge_up_mm_one<float>(host_args<hx::MmMergeArgs<float>>(blob, g), b, g.nt, s);
-    case K_MD_D: return hx::launch_merge_down_mm_one<double>(host_args<hx::MmMergeArgs<double>>(blob, g), b, g.nt, s);
-    case K_MD_F: return hx::launch_merge_down_mm_one<float>(host_args<hx::MmMergeArgs<float>>(blob, g), b, g.nt, s);
+    case K_MU_D: return hx::launch_merge_up_mm_one<double>(host_args<hx::MmMergeArgs<double>>(blob, g), b, g.nt, g.wv, s);
+    case K_MU_F: return hx::launch_merge_up_mm_one<float>(host_args<hx::MmMergeArgs<float>>(blob, g), b, g.nt, g.wv, s);
+    case K_MD_D: return hx::launch_merge_down_mm_one<double>(host_args<hx::MmMergeArgs<double>>(blob, g), b, g.nt, g.wv, s);
+    case K_MD_F: return hx::launch_merge_down_mm_one<float>(host_args<hx::MmMergeArgs<float>>(blob, g), b, g.nt, g.wv, s);
     case K_LD_D: return hx::launch_leaf_down_mm_one<double>(host_args<hx::MmLeafDownArgs<double>>(blob, g), b, g.nt, s);
     case K_LD_F: return hx::launch_leaf_down_mm_one<float>(host_args<hx::MmLeafDownArgs<float>>(blob, g), b, g.nt, s);
     case K_LDS_D: return hx::launch_leaf_down_sum_mm_one<double>(host_args<hx::MmLeafDownArgs<double>>(blob, g), b, g.nt, s);
@@ -1568,10 +1583,10 @@ hipError_t launch_group(const hx_plan* plan, const Group& g, const unsigned char
   switch (g.kind) {
     case K_LU_D: return hx::launch_leaf_up_mm_multi<double>(multi_of<hx::MmLeafUpArgs<double>>(plan, g), b, g.nt, g.lds, s);
     case K_LU_F: return hx::launch_leaf_up_mm_multi<float>(multi_of<hx::MmLeafUpArgs<float>>(plan, g), b, g.nt, g.lds, s);
-    case K_MU_D: return hx::launch_merge_up_mm_multi<double>(multi_of<hx::MmMergeArgs<double>>(plan, g), b, g.nt, s);
-    case K_MU_F: return hx::launch_merge_up_mm_multi<float>(multi_of<hx::MmMergeArgs<float>>(plan, g), b, g.nt, s);
-    case K_MD_D: return hx::launch_merge_down_mm_multi<double>(multi_of<hx::MmMergeArgs<double>>(plan, g), b, g.nt, s);
-    case K_MD_F: return hx::launch_merge_down_mm_multi<float>(multi_of<hx::MmMergeArgs<float>>(plan, g), b, g.nt, s);
+    case K_MU_D: return hx::launch_merge_up_mm_multi<double>(multi_of<hx::MmMergeArgs<double>>(plan, g), b, g.nt, g.wv, s);
+    case K_MU_F: return hx::launch_merge_up_mm_multi<float>(multi_of<hx::MmMergeArgs<float>>(plan, g), b, g.nt, g.wv, s);
+    case K_MD_D: return hx::launch_merge_down_mm_multi<double>(multi_of<hx::MmMergeArgs<double>>(plan, g), b, g.nt, g.wv, s);
+    case K_MD_F: return hx::launch_merge_down_mm_multi<float>(multi_of<hx::MmMergeArgs<float>>(plan, g), b, g.nt, g.wv, s);
     case K_LD_D: return hx::launch_leaf_down_mm_multi<double>(multi_of<hx::MmLeafDownArgs<double>>(plan, g), b, g.nt, s);
     case K_LD_F: return hx::launch_leaf_down_mm_multi<float>(multi_of<hx::MmLeafDownArgs<float>>(plan, g), b, g.nt, s);
     case K_LDS_D: return hx::launch_leaf_down_sum_mm_multi<double>(multi_of<hx::MmLeafDownArgs<double>>(plan, g), b, g.nt, s);
@@ -1616,19 +1631,27 @@ hx_status prepare_tables(hx_plan* plan, double* const* states, hipStream_t s) {
 // order of the HX_STAGE_* codes.
 constexpr int kTunedOrders[HX_STAGES] = {O_LEAF_UP, O_MERGE_UP, O_ROOT, O_MERGE_DOWN, O_LEAF_DOWN};
 
-// Autotuner: for every batched instance with more than 16 right-hand sides
-// and every tuned stage, launch that stage of the first sweep (all its
-// levels) with one and with two tiles per block on a scratch state in the
-// build workspace, time the better of three runs of each, keep the faster.
+// Autotuner: for every batched instance and every tuned stage, launch that
+// stage of the first sweep (all its levels) in each candidate shape on a
+// scratch state in the build workspace, time the best of three runs of
+// each, keep the fastest.  Candidates: 1 or 2 right-hand-side tiles per
+// block (more than 16 right-hand sides only); for the merge stages also
+// one-wave blocks at every level against the level rule of merge_wv.
 template <class T>
 hx_status tune_instance(hx_plan* plan, Instance& I, int k, double* scratch, hipStream_t s,
                         hipEvent_t e0, hipEvent_t e1) {
   for (int st = 0; st < HX_STAGES; ++st) {
     const int order = kTunedOrders[st];
+    const bool merge = order == O_MERGE_UP || order == O_MERGE_DOWN;
+    std::vector<std::pair<int, int>> cand;   // (tiles, waves mode)
+    for (int nt = 1; nt <= (I.nrhs > 16 ? 2 : 1); ++nt)
+      for (int wv = 0; wv <= (merge ? 1 : 0); ++wv) cand.push_back({nt, wv});
+    if (cand.size() < 2) continue;
     float best = 1e30f;
-    int best_nt = 0;
-    for (int nt = 1; nt <= 2; ++nt) {
-      I.tune_nt[order] = nt;
+    std::pair<int, int> best_c{0, 0};
+    for (const auto& c : cand) {
+      I.tune_nt[order] = I.nrhs > 16 ? c.first : 0;
+      I.tune_wv[order] = c.second;
       Recorder R;
       record_instance<T>(plan, I, k, scratch, R);
       Recorder one;
@@ -1653,10 +1676,11 @@ hx_status tune_instance(hx_plan* plan, Instance& I, int k, double* scratch, hipS
       }
       if (t_min < best) {
         best = t_min;
-        best_nt = nt;
+        best_c = c;
       }
     }
-    I.tune_nt[order] = best_nt;
+    I.tune_nt[order] = I.nrhs > 16 ? best_c.first : 0;
+    I.tune_wv[order] = best_c.second;
   }
   return HX_OK;
 }
@@ -1669,7 +1693,7 @@ hx_status autotune(hx_plan* plan, char* ws, size_t ws_bytes, hipStream_t s) {
   hx_status st = HX_OK;
   for (size_t k = 0; k < plan->inst.size() && st == HX_OK; ++k) {
     Instance& I = plan->inst[k];
-    if (!batched(plan, I) || I.nrhs <= 16) continue;
+    if (!batched(plan, I)) continue;
     const size_t need = sizeof(double) * (size_t)I.nfield * I.n_leaf * I.q2 * I.nrhs;
     if (need > ws_bytes) continue;                 // no room for a scratch state: default rule
     double* scratch = reinterpret_cast<double*>(ws);
