@@ -178,95 +178,148 @@ __device__ __forceinline__ void mm_emit(const Acc<T, NT>& acc, int row0, int nro
 
 constexpr int kKC = 64;  // k-chunk of B staged in LDS
 
-// ---- leaf upward: g from the state, w = W g, h = N_i w ------------------------
-// block = (leaf, pole, rhs tile); every row tile of W is handled by the block.
-template <class T, int NT>
+// ---- leaf upward: g from the sources, w = W g, h = N_i w -------------------------
+// block = (leaf, rhs tile, group of pole_group poles); it stages the source
+// fields of its element and right-hand sides once in LDS, then walks its
+// poles: g_m = k1 X1 + k2 X2 + k3 X3 (or the residual gin), w = W_m g on the
+// matrix cores, h = N_i w from an LDS copy of w (w_lds) or from memory.
+// XL: the source fields are staged in LDS once per block (else read per pole).
+template <class T, int NT, bool XL>
 __device__ __forceinline__ void leaf_up_body(const MmLeafUpArgs<T>& a, const int bid) {
   using C = typename MM<T>::C;
-  constexpr int RT = 16 * NT, BST = RT + 1;
+  constexpr int RT = 16 * NT, BST = RT + 1, LRT = NT == 2 ? 5 : 4;   // LRT = log2(RT)
   extern __shared__ unsigned char smem[];
-  C* gs = reinterpret_cast<C*>(smem);
   const int n_rt = (a.nrhs + RT - 1) / RT;
-  const int rt = bid % n_rt;
-  const int lp = bid / n_rt;
-  const int pole = lp % a.npole, leaf = lp / a.npole;
+  const int G = a.pole_group, npg = (a.npole + G - 1) / G;
+  int rest = bid;
+  const int rt = rest % n_rt; rest /= n_rt;
+  const int pg = rest % npg;
+  const int leaf = rest / npg;
+  const int p_lo = pg * G, p_hi = min(a.npole, p_lo + G);
   const int q = a.q, q2 = q * q, q2p = (q2 + 3) & ~3;
   const LeafDesc L = a.leaves[leaf];
-  const PoleCoef pc = a.coef[pole];
-  const int r = a.nrhs;
-  for (int idx = threadIdx.x; idx < q2p * RT; idx += blockDim.x) {
-    const int j = idx / q2p, k = idx - j * q2p;
-    const int rhs = rt * RT + j;
-    C g;
-    g.x = g.y = T(0);
-    if (k < q2 && rhs < r) {
-      if (a.gin) {
-        g = a.gin[((long long)pole * a.w_pole + (long long)leaf * q2 + k) * r + rhs];
-      } else {
-        const double* x1 = a.state + rhs * a.rhs_stride + (long long)L.elem * q2;
-        const double u1 = x1[k], u2 = x1[a.n_int + k];
-        const double u3 = a.nsrc > 2 ? x1[2 * a.n_int + k] : 0.0;
+  const int r = a.nrhs, ns = a.nsrc;
+  C* gs = reinterpret_cast<C*>(smem);                        // g [q2p][BST]
+  C* wl = gs + q2p * BST;                                    // w tile [q2][RT]
+  T* xs = reinterpret_cast<T*>(wl + (a.w_lds ? q2 * RT : 0));   // sources [ns][q2p][RT] (x_lds)
+  const bool xl = XL && !a.gin;
+  T* nrl = xs + (xl ? ns * q2p * RT : 0);                    // normal-derivative rows [2q]
+  int* hmt = reinterpret_cast<int*>(nrl + 2 * q);            // edge slot -> side | t << 2
+  if (xl) {
+    // k fastest so that the state reads are contiguous (one-time divisions)
+    for (int idx = threadIdx.x; idx < ns * RT * q2p; idx += blockDim.x) {
+      const int k = idx % q2p, fj = idx / q2p;
+      const int j = fj % RT, f = fj / RT;
+      const int rhs = rt * RT + j;
+      T v = T(0);
+      if (k < q2 && rhs < r)
+        v = T(a.state[rhs * a.rhs_stride + (long long)f * a.n_int + (long long)L.elem * q2 + k]);
+      xs[(f * q2p + k) * RT + j] = v;
+    }
+  }
+  for (int t = threadIdx.x; t < 2 * q; t += blockDim.x) nrl[t] = T(a.nrow[t]);
+  for (int k = threadIdx.x; k < L.e; k += blockDim.x) {
+    const int slot = k / q;
+    int sd = -1, seen = -1;
+    for (int m = 0; m < 4; ++m)
+      if ((L.side_mask >> m) & 1)
+        if (++seen == slot) { sd = m; break; }
+    hmt[k] = sd | ((k - slot * q) << 2);
+  }
+  const int wave = threadIdx.x >> 6;
+  for (int pole = p_lo; pole < p_hi; ++pole) {
+    // g of this pole, rhs fastest (all LDS, or contiguous gin rows)
+    if (a.gin) {
+      const C* gp = a.gin + ((long long)pole * a.w_pole + (long long)leaf * q2) * r + rt * RT;
+      for (int idx = threadIdx.x; idx < q2p * RT; idx += blockDim.x) {
+        const int j = idx & (RT - 1), k = idx >> LRT;
+        C g;
+        g.x = g.y = T(0);
+        if (k < q2 && rt * RT + j < r) g = gp[(long long)k * r + j];
+        gs[k * BST + j] = g;
+      }
+    } else if (!XL) {
+      // sources read from memory (k fastest: contiguous state rows)
+      __syncthreads();
+      const PoleCoef pc = a.coef[pole];
+      for (int idx = threadIdx.x; idx < q2p * RT; idx += blockDim.x) {
+        const int j = idx / q2p, k = idx - j * q2p;
+        const int rhs = rt * RT + j;
+        C g;
+        g.x = g.y = T(0);
+        if (k < q2 && rhs < r) {
+          // sources rounded to T as when staged, so that both ways give
+          // the same g (the FP64 residual of the precision form corrects it)
+          const double* x1 = a.state + rhs * a.rhs_stride + (long long)L.elem * q2;
+          const double u1 = double(T(x1[k])), u2 = double(T(x1[a.n_int + k]));
+          const double u3 = ns > 2 ? double(T(x1[2 * a.n_int + k])) : 0.0;
+          g.x = T(fma(pc.k1.x, u1, fma(pc.k2.x, u2, pc.k3.x * u3)));
+          g.y = T(fma(pc.k1.y, u1, fma(pc.k2.y, u2, pc.k3.y * u3)));
+        }
+        gs[k * BST + j] = g;
+      }
+    } else {
+      __syncthreads();   // sources staged / previous pole done with gs
+      const PoleCoef pc = a.coef[pole];
+      for (int idx = threadIdx.x; idx < q2p * RT; idx += blockDim.x) {
+        const int j = idx & (RT - 1), k = idx >> LRT;
+        const double u1 = double(xs[k * RT + j]), u2 = double(xs[(q2p + k) * RT + j]);
+        const double u3 = ns > 2 ? double(xs[(2 * q2p + k) * RT + j]) : 0.0;
+        C g;
         g.x = T(fma(pc.k1.x, u1, fma(pc.k2.x, u2, pc.k3.x * u3)));
         g.y = T(fma(pc.k1.y, u1, fma(pc.k2.y, u2, pc.k3.y * u3)));
+        gs[k * BST + j] = g;
       }
     }
-    gs[k * BST + j] = g;
-  }
-  __syncthreads();
-  const C* W = a.ops + pole * a.pole_stride + L.op_off;
-  C* w = a.w + ((long long)pole * a.w_pole + (long long)leaf * q2) * r;
-  // with w_lds the block also keeps its w tile [q^2][RT] in LDS after the
-  // staged g, so that h = N_i w does not read w back from memory
-  C* wl = gs + q2p * BST;
-  const int wave = threadIdx.x >> 6;
-  for (int tile = wave; tile * 16 < q2; tile += kBlock / 64) {
-    Acc<T, NT> acc;
-    acc.zero();
-    mm_chunk<T, NT>(acc, W, q2, tile * 16, q2, 0, q2, gs, BST);
-    mm_emit<T, NT>(acc, tile * 16, q2, [&](int row, int j, C c) {
-      const int rhs = rt * RT + j;
-      if (rhs < r) w[(long long)row * r + rhs] = c;
-      if (a.w_lds) wl[row * RT + j] = c;
-    });
-  }
-  __syncthreads();
-  C* h = a.h + ((long long)pole * a.h_pole + L.vec_off) * r;
-  for (int idx = threadIdx.x; idx < L.e * RT; idx += blockDim.x) {
-    const int re = idx / RT, j = idx - re * RT;
-    const int rhs = rt * RT + j;
-    if (rhs >= r) continue;
-    const int slot = re / q, t = re - slot * q;
-    int s = -1, seen = -1;
-    for (int k = 0; k < 4; ++k)
-      if ((L.side_mask >> k) & 1)
-        if (++seen == slot) { s = k; break; }
-    const double* nr = a.nrow + ((s == 1 || s == 3) ? q : 0);
-    const double sc = (s == 0) ? -a.sx : (s == 1) ? a.sx : (s == 2) ? -a.sy : a.sy;
-    T sx_ = T(0), sy_ = T(0);
-    for (int k = 0; k < q; ++k) {
-      const int node = (s < 2) ? (k + q * t) : (t + q * k);
-      const C wv = a.w_lds ? wl[node * RT + j] : w[(long long)node * r + rhs];
-      sx_ += T(nr[k]) * wv.x;
-      sy_ += T(nr[k]) * wv.y;
+    __syncthreads();
+    const C* W = a.ops + pole * a.pole_stride + L.op_off;
+    C* w = a.w + ((long long)pole * a.w_pole + (long long)leaf * q2) * r;
+    for (int tile = wave; tile * 16 < q2; tile += kBlock / 64) {
+      Acc<T, NT> acc;
+      acc.zero();
+      mm_chunk<T, NT>(acc, W, q2, tile * 16, q2, 0, q2, gs, BST);
+      mm_emit<T, NT>(acc, tile * 16, q2, [&](int row, int j, C c) {
+        const int rhs = rt * RT + j;
+        if (rhs < r) w[(long long)row * r + rhs] = c;
+        if (a.w_lds) wl[row * RT + j] = c;
+      });
     }
-    C hv;
-    hv.x = T(sc) * sx_;
-    hv.y = T(sc) * sy_;
-    h[(long long)re * r + rhs] = hv;
+    __syncthreads();
+    C* h = a.h + ((long long)pole * a.h_pole + L.vec_off) * r;
+    for (int idx = threadIdx.x; idx < L.e * RT; idx += blockDim.x) {
+      const int j = idx & (RT - 1), re = idx >> LRT;
+      const int rhs = rt * RT + j;
+      if (rhs >= r) continue;
+      const int hm = hmt[re], sd = hm & 3, t = hm >> 2;
+      const T* nr = nrl + ((sd == 1 || sd == 3) ? q : 0);
+      const T sc = T((sd == 0) ? -a.sx : (sd == 1) ? a.sx : (sd == 2) ? -a.sy : a.sy);
+      T sx_ = T(0), sy_ = T(0);
+      for (int k = 0; k < q; ++k) {
+        const int node = (sd < 2) ? (k + q * t) : (t + q * k);
+        const C wv = a.w_lds ? wl[node * RT + j] : w[(long long)node * r + rhs];
+        sx_ += nr[k] * wv.x;
+        sy_ += nr[k] * wv.y;
+      }
+      C hv;
+      hv.x = sc * sx_;
+      hv.y = sc * sy_;
+      h[(long long)re * r + rhs] = hv;
+    }
+    if (a.gin) __syncthreads();   // the next pole's gin staging overwrites gs
   }
 }
 
-template <class T, int NT>
+template <class T, int NT, bool XL>
 __global__ __launch_bounds__(kBlock) void k_leaf_up_mm(MmLeafUpArgs<T> a) {
-  leaf_up_body<T, NT>(a, blockIdx.x);
+  leaf_up_body<T, NT, XL>(a, blockIdx.x);
 }
 
-template <class T, int NT>
+template <class T, int NT, bool XL>
 __global__ __launch_bounds__(kBlock) void k_leaf_up_mm_multi(Multi<MmLeafUpArgs<T>> m) {
   int i;
   const int bid = m.locate(blockIdx.x, i);
   const MmLeafUpArgs<T> a = m.args[i];
-  leaf_up_body<T, NT>(a, bid);
+  leaf_up_body<T, NT, XL>(a, bid);
 }
 
 // ---- merge upward: g3 = h3a + h3b (- j3), h_par = [h1a; h2b] - Y g3 ----------
@@ -655,95 +708,22 @@ __global__ __launch_bounds__(kBlock) void k_sw_root_mm_multi(Multi<SwRootArgs<T>
   sw_root_body<T, NT>(a, bid);
 }
 
-template <class T>
-hipError_t launch_sw_root_mm(const SwRootArgs<T>& a, hipStream_t s) {
-  const int nt = a.nrhs > 16 ? 2 : 1;
-  const int RT = 16 * nt;
-  const int n_rt = (a.nrhs + RT - 1) / RT;
-  const dim3 grid(a.npole * n_rt * a.row_groups);
-  if (nt == 2) hipLaunchKernelGGL((k_sw_root_mm<T, 2>), grid, dim3(kBlock), 0, s, a);
-  else hipLaunchKernelGGL((k_sw_root_mm<T, 1>), grid, dim3(kBlock), 0, s, a);
-  return hipGetLastError();
-}
 
-template hipError_t launch_sw_root_mm<double>(const SwRootArgs<double>&, hipStream_t);
-template hipError_t launch_sw_root_mm<float>(const SwRootArgs<float>&, hipStream_t);
 
 // ---- launchers -----------------------------------------------------------------
 
 template <class T, int NT>
-size_t leaf_up_lds(int q, bool with_w = false) {
-  return sizeof(typename MM<T>::C) *
-         ((size_t)((q * q + 3) & ~3) * (16 * NT + 1) + (with_w ? (size_t)q * q * 16 * NT : 0));
-}
-
-template <class T, int NT>
-static hipError_t leaf_up_t(const MmLeafUpArgs<T>& a, int n_leaf, hipStream_t s) {
-  constexpr int RT = 16 * NT;
-  const size_t lds = leaf_up_lds<T, NT>(a.q);
-  if (lds > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf_up_mm<T, NT>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  const int n_rt = (a.nrhs + RT - 1) / RT;
-  hipLaunchKernelGGL((k_leaf_up_mm<T, NT>), dim3(n_leaf * a.npole * n_rt), dim3(kBlock), lds, s, a);
-  return hipGetLastError();
-}
-
-// Two tiles of 16 right-hand sides per block when the staged right-hand
-// sides fit in 64 KiB of LDS, otherwise one (more blocks, W read per tile).
-template <class T>
-hipError_t launch_leaf_up_mm(const MmLeafUpArgs<T>& a, int n_leaf, int nt, hipStream_t s) {
-  if (nt == 2 && leaf_up_lds<T, 2>(a.q) <= 65536) return leaf_up_t<T, 2>(a, n_leaf, s);
-  return leaf_up_t<T, 1>(a, n_leaf, s);
-}
-
-template <class T>
-hipError_t launch_merge_up_mm(const MmMergeArgs<T>& a, int n_box, int nt, hipStream_t s) {
-  const int RT = 16 * nt;
-  const int n_rt = (a.nrhs + RT - 1) / RT;
-  const dim3 grid(n_box * a.npole * n_rt * a.row_groups);
-  if (nt == 2) hipLaunchKernelGGL((k_merge_up_mm<T, 2>), grid, dim3(kBlock), 0, s, a);
-  else hipLaunchKernelGGL((k_merge_up_mm<T, 1>), grid, dim3(kBlock), 0, s, a);
-  return hipGetLastError();
-}
-
-template <class T>
-hipError_t launch_merge_down_mm(const MmMergeArgs<T>& a, int n_box, int nt, hipStream_t s) {
-  const int RT = 16 * nt;
-  const int n_rt = (a.nrhs + RT - 1) / RT;
-  const dim3 grid(n_box * a.npole * n_rt * a.row_groups);
-  if (nt == 2) hipLaunchKernelGGL((k_merge_down_mm<T, 2>), grid, dim3(kBlock), 0, s, a);
-  else hipLaunchKernelGGL((k_merge_down_mm<T, 1>), grid, dim3(kBlock), 0, s, a);
-  return hipGetLastError();
-}
-
-template <class T>
-hipError_t launch_leaf_down_mm(const MmLeafDownArgs<T>& a, int n_leaf, int nt, hipStream_t s) {
-  const int RT = 16 * nt;
-  const int n_rt = (a.nrhs + RT - 1) / RT;
-  const dim3 grid(n_leaf * a.npole * n_rt * a.row_groups);
-  if (nt == 2) hipLaunchKernelGGL((k_leaf_down_mm<T, 2>), grid, dim3(kBlock), 0, s, a);
-  else hipLaunchKernelGGL((k_leaf_down_mm<T, 1>), grid, dim3(kBlock), 0, s, a);
-  return hipGetLastError();
-}
-
-template <class T>
-hipError_t launch_leaf_down_sum_mm(const MmLeafDownArgs<T>& a, int n_leaf, int nt, hipStream_t s) {
-  const int RT = 16 * nt;
-  const int n_rt = (a.nrhs + RT - 1) / RT;
-  const dim3 grid(n_leaf * n_rt * a.row_groups);
-  if (nt == 2) hipLaunchKernelGGL((k_leaf_down_sum_mm<T, 2>), grid, dim3(kBlock), 0, s, a);
-  else hipLaunchKernelGGL((k_leaf_down_sum_mm<T, 1>), grid, dim3(kBlock), 0, s, a);
-  return hipGetLastError();
+size_t leaf_up_lds(int q, bool with_w = false, int nsrc_staged = 0) {
+  const size_t q2 = (size_t)q * q, q2p = (q2 + 3) & ~(size_t)3, RT = 16 * NT;
+  return sizeof(typename MM<T>::C) * (q2p * (RT + 1) + (with_w ? q2 * RT : 0)) +
+         sizeof(T) * ((size_t)nsrc_staged * q2p * RT + 2 * (size_t)q) + sizeof(int) * 4 * (size_t)q;
 }
 
 // ---- multi-instance launchers ------------------------------------------------------
 
 template <class T>
-size_t leaf_up_lds_bytes(int q, int nt, bool with_w) {
-  return nt == 2 ? leaf_up_lds<T, 2>(q, with_w) : leaf_up_lds<T, 1>(q, with_w);
+size_t leaf_up_lds_bytes(int q, int nt, bool with_w, int nsrc_staged) {
+  return nt == 2 ? leaf_up_lds<T, 2>(q, with_w, nsrc_staged) : leaf_up_lds<T, 1>(q, with_w, nsrc_staged);
 }
 
 template <class K>
@@ -753,20 +733,35 @@ static hipError_t allow_lds(K* kernel, size_t lds) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <class T>
-hipError_t launch_leaf_up_mm_multi(const Multi<MmLeafUpArgs<T>>& m, int blocks, int nt, size_t lds,
-                                   hipStream_t s) {
-  if (blocks <= 0) return hipSuccess;
-  if (nt == 2) {
-    const hipError_t e = allow_lds(&k_leaf_up_mm_multi<T, 2>, lds);
+template <class T, int NT, bool XL>
+static hipError_t leaf_up_launch(const MmLeafUpArgs<T>* a, const Multi<MmLeafUpArgs<T>>* m,
+                                 int blocks, size_t lds, hipStream_t s) {
+  if (a) {
+    const hipError_t e = allow_lds(&k_leaf_up_mm<T, NT, XL>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_leaf_up_mm_multi<T, 2>), dim3(blocks), dim3(kBlock), lds, s, m);
+    hipLaunchKernelGGL((k_leaf_up_mm<T, NT, XL>), dim3(blocks), dim3(kBlock), lds, s, *a);
   } else {
-    const hipError_t e = allow_lds(&k_leaf_up_mm_multi<T, 1>, lds);
+    const hipError_t e = allow_lds(&k_leaf_up_mm_multi<T, NT, XL>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_leaf_up_mm_multi<T, 1>), dim3(blocks), dim3(kBlock), lds, s, m);
+    hipLaunchKernelGGL((k_leaf_up_mm_multi<T, NT, XL>), dim3(blocks), dim3(kBlock), lds, s, *m);
   }
   return hipGetLastError();
+}
+
+template <class T>
+static hipError_t leaf_up_dispatch(const MmLeafUpArgs<T>* a, const Multi<MmLeafUpArgs<T>>* m,
+                                   int blocks, int nt, bool xl, size_t lds, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  if (nt == 2) return xl ? leaf_up_launch<T, 2, true>(a, m, blocks, lds, s)
+                         : leaf_up_launch<T, 2, false>(a, m, blocks, lds, s);
+  return xl ? leaf_up_launch<T, 1, true>(a, m, blocks, lds, s)
+            : leaf_up_launch<T, 1, false>(a, m, blocks, lds, s);
+}
+
+template <class T>
+hipError_t launch_leaf_up_mm_multi(const Multi<MmLeafUpArgs<T>>& m, int blocks, int nt, bool xl,
+                                   size_t lds, hipStream_t s) {
+  return leaf_up_dispatch<T>(nullptr, &m, blocks, nt, xl, lds, s);
 }
 
 #define HX_MULTI_LAUNCHER(NAME, ARGS)                                                          \
@@ -786,17 +781,7 @@ HX_MULTI_LAUNCHER(sw_root_mm, SwRootArgs)
 // instance skips the table lookup), same block counts as the multi form.
 template <class T>
 hipError_t launch_leaf_up_mm_one(const MmLeafUpArgs<T>& a, int blocks, int nt, size_t lds, hipStream_t s) {
-  if (blocks <= 0) return hipSuccess;
-  if (nt == 2) {
-    const hipError_t e = allow_lds(&k_leaf_up_mm<T, 2>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_leaf_up_mm<T, 2>), dim3(blocks), dim3(kBlock), lds, s, a);
-  } else {
-    const hipError_t e = allow_lds(&k_leaf_up_mm<T, 1>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_leaf_up_mm<T, 1>), dim3(blocks), dim3(kBlock), lds, s, a);
-  }
-  return hipGetLastError();
+  return leaf_up_dispatch<T>(&a, nullptr, blocks, nt, a.x_lds != 0, lds, s);
 }
 
 #define HX_ONE_LAUNCHER(NAME, ARGS)                                                            \
@@ -844,8 +829,8 @@ HX_MERGE_LAUNCHERS(merge_down_mm)
 #undef HX_MERGE_LAUNCHERS
 
 #define HX_INST(T)                                                                                     \
-  template size_t leaf_up_lds_bytes<T>(int, int, bool);                                                      \
-  template hipError_t launch_leaf_up_mm_multi<T>(const Multi<MmLeafUpArgs<T>>&, int, int, size_t, hipStream_t); \
+  template size_t leaf_up_lds_bytes<T>(int, int, bool, int);                                                      \
+  template hipError_t launch_leaf_up_mm_multi<T>(const Multi<MmLeafUpArgs<T>>&, int, int, bool, size_t, hipStream_t); \
   template hipError_t launch_merge_up_mm_multi<T>(const Multi<MmMergeArgs<T>>&, int, int, int, hipStream_t);   \
   template hipError_t launch_merge_down_mm_multi<T>(const Multi<MmMergeArgs<T>>&, int, int, int, hipStream_t); \
   template hipError_t launch_leaf_down_mm_multi<T>(const Multi<MmLeafDownArgs<T>>&, int, int, hipStream_t); \
@@ -861,15 +846,5 @@ HX_INST(float)
 HX_INST(double)
 #undef HX_INST
 
-template hipError_t launch_leaf_down_sum_mm<double>(const MmLeafDownArgs<double>&, int, int, hipStream_t);
-template hipError_t launch_leaf_down_sum_mm<float>(const MmLeafDownArgs<float>&, int, int, hipStream_t);
-template hipError_t launch_leaf_up_mm<float>(const MmLeafUpArgs<float>&, int, int, hipStream_t);
-template hipError_t launch_merge_up_mm<float>(const MmMergeArgs<float>&, int, int, hipStream_t);
-template hipError_t launch_merge_down_mm<float>(const MmMergeArgs<float>&, int, int, hipStream_t);
-template hipError_t launch_leaf_down_mm<float>(const MmLeafDownArgs<float>&, int, int, hipStream_t);
-template hipError_t launch_leaf_up_mm<double>(const MmLeafUpArgs<double>&, int, int, hipStream_t);
-template hipError_t launch_merge_up_mm<double>(const MmMergeArgs<double>&, int, int, hipStream_t);
-template hipError_t launch_merge_down_mm<double>(const MmMergeArgs<double>&, int, int, hipStream_t);
-template hipError_t launch_leaf_down_mm<double>(const MmLeafDownArgs<double>&, int, int, hipStream_t);
 
 }  // namespace hx

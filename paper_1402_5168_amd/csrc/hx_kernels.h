@@ -122,6 +122,8 @@ struct MmLeafUpArgs {
   // residual [pole][leaf][q*q][rhs] instead of the state (null: state)
   const typename Cplx<T>::type* gin;
   int w_lds;                 // keep the w tile in LDS for h (the launch's LDS allows it)
+  int pole_group;            // poles walked by one block (blocks: leaves x tiles x groups)
+  int x_lds;                 // stage the source fields in LDS once per block (else read per pole)
 };
 
 template <class T>
@@ -232,11 +234,7 @@ struct SwRootArgs {
   const int4* wall_info;
 };
 
-hipError_t launch_sw_prep(const SwPrepArgs& a, int n_leaf, hipStream_t s);
-hipError_t launch_sw_wall(const SwWallArgs& a, hipStream_t s);
 hipError_t launch_sw_root_form(const SwRootFormArgs& a, int chunk, hipStream_t s);
-template <class T> hipError_t launch_sw_post(const SwPostArgs<T>& a, int n_leaf, hipStream_t s);
-template <class T> hipError_t launch_sw_root_mm(const SwRootArgs<T>& a, hipStream_t s);
 hipError_t launch_sw_prep_multi(const Multi<SwPrepArgs>& m, int blocks, hipStream_t s);
 hipError_t launch_sw_wall_multi(const Multi<SwWallArgs>& m, int blocks, hipStream_t s);
 template <class T>
@@ -274,7 +272,6 @@ struct ResidualArgs {
   double* esum;              // first-sweep pole sums E0, E1, E2 [leaf][3][p*p][rhs]
   int RR;                    // right-hand sides per block (set by residual_rr)
 };
-hipError_t launch_residual(const ResidualArgs& a, int n_leaf, hipStream_t s);
 int residual_rr(const ResidualArgs& a);                       // RR for one instance
 size_t residual_lds_bytes(int p, int RR, int nsrc);
 hipError_t launch_residual_multi(const Multi<ResidualArgs>& m, int blocks, bool sw, size_t lds,
@@ -282,7 +279,7 @@ hipError_t launch_residual_multi(const Multi<ResidualArgs>& m, int blocks, bool 
 
 // Multi-instance variants: one launch over the blocks of every instance in
 // the table, all with the same tile count nt (1 or 2) and LDS bytes.
-template <class T> hipError_t launch_leaf_up_mm_multi(const Multi<MmLeafUpArgs<T>>& m, int blocks, int nt, size_t lds, hipStream_t s);
+template <class T> hipError_t launch_leaf_up_mm_multi(const Multi<MmLeafUpArgs<T>>& m, int blocks, int nt, bool xl, size_t lds, hipStream_t s);
 template <class T> hipError_t launch_merge_up_mm_multi(const Multi<MmMergeArgs<T>>& m, int blocks, int nt, int wv, hipStream_t s);
 template <class T> hipError_t launch_merge_down_mm_multi(const Multi<MmMergeArgs<T>>& m, int blocks, int nt, int wv, hipStream_t s);
 template <class T> hipError_t launch_leaf_down_mm_multi(const Multi<MmLeafDownArgs<T>>& m, int blocks, int nt, hipStream_t s);
@@ -302,14 +299,9 @@ template <class T>
 hipError_t launch_sw_post_one(const SwPostArgs<T>& a, int blocks, size_t lds, hipStream_t s);
 // LDS bytes of the leaf upward kernel (above 64 KiB the launcher raises the
 // kernel's dynamic LDS limit).
-template <class T> size_t leaf_up_lds_bytes(int q, int nt, bool with_w);
+template <class T> size_t leaf_up_lds_bytes(int q, int nt, bool with_w, int nsrc_staged);
 
 // nt = right-hand-side tiles of 16 per block (1 or 2)
-template <class T> hipError_t launch_leaf_up_mm(const MmLeafUpArgs<T>& a, int n_leaf, int nt, hipStream_t s);
-template <class T> hipError_t launch_merge_up_mm(const MmMergeArgs<T>& a, int n_box, int nt, hipStream_t s);
-template <class T> hipError_t launch_merge_down_mm(const MmMergeArgs<T>& a, int n_box, int nt, hipStream_t s);
-template <class T> hipError_t launch_leaf_down_mm(const MmLeafDownArgs<T>& a, int n_leaf, int nt, hipStream_t s);
-template <class T> hipError_t launch_leaf_down_sum_mm(const MmLeafDownArgs<T>& a, int n_leaf, int nt, hipStream_t s);
 
 // ---- build stage ------------------------------------------------------------
 

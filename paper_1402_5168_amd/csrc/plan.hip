@@ -111,6 +111,7 @@ struct Instance {
   double max_abs_R = 0.0, fit_X = 0.0, sum_abs_b = 0.0;
   int tune_nt[8] = {0, 0, 0, 0, 0, 0, 0, 0}; // per stage: right-hand-side tiles (0: default)
   int tune_wv[8] = {0, 0, 0, 0, 0, 0, 0, 0}; // merge stages: 1 = one-wave blocks at every level
+  int tune_xl = 0;                          // upward elements: 2 = never stage the sources
   bool fp32 = false;                        // precision form: FP32 operators and sweeps
   // shallow water: wall nodes are exterior unknowns up to the root
   bool sw = false;
@@ -1172,7 +1173,7 @@ enum StageOrder : int { O_PREP, O_LEAF_UP, O_MERGE_UP, O_ROOT, O_MERGE_DOWN, O_L
 
 
 struct Rec {
-  int pass, order, level, kind, nt, wv, cls, inst;
+  int pass, order, level, kind, nt, wv, cls, inst;   // wv: merge waves / leaf staging variant
   long long blocks;
   size_t lds, args_size;
   unsigned char args[kArgsMax];
@@ -1296,14 +1297,30 @@ void record_instance(const hx_plan* plan, const Instance& I, int inst, double* s
     lu.h = vec(I.levels[0].d_h);
     lu.h_pole = I.levels[0].total_ext;
     lu.gin = pass ? gres : nullptr;
-    // two tiles only while the staged right-hand sides fit in 64 KiB of LDS;
-    // the w tile joins them in LDS when the total stays within 64 KiB
+    // LDS: staged g, the w tile for h (when it fits), the staged source
+    // fields (first sweep); two tiles only while g and the sources fit in
+    // 64 KiB, and the w tile only while the total does
+    // Staging the sources once per block and walking a group of poles pays
+    // when the sources fit beside the staged g; otherwise one pole per block
+    // reads them per pole (the tuner may also choose that on purpose).
     int nt = stage_nt(I, O_LEAF_UP);
-    if (nt == 2 && hx::leaf_up_lds_bytes<T>(I.q, 2, false) > 65536) nt = 1;
-    lu.w_lds = hx::leaf_up_lds_bytes<T>(I.q, nt, true) <= 65536 ? 1 : 0;
-    const size_t lds = hx::leaf_up_lds_bytes<T>(I.q, nt, lu.w_lds != 0);
-    R.add(pass, O_LEAF_UP, 0, dbl ? K_LU_D : K_LU_F, nt,
-          (long long)I.n_leaf * I.npole * hx::mm_tiles(I.nrhs, nt), lds, lu, HX_K_LEAF_UP, inst);
+    if (nt == 2 && hx::leaf_up_lds_bytes<T>(I.q, 2, false, 0) > 65536) nt = 1;
+    const bool xl = !pass && I.tune_xl != 2 &&
+                    hx::leaf_up_lds_bytes<T>(I.q, nt, false, lu.nsrc) <= 65536;
+    const int staged = xl ? lu.nsrc : 0;
+    lu.x_lds = xl ? 1 : 0;
+    lu.w_lds = hx::leaf_up_lds_bytes<T>(I.q, nt, true, staged) <= 65536 ? 1 : 0;
+    const size_t lds = hx::leaf_up_lds_bytes<T>(I.q, nt, lu.w_lds != 0, staged);
+    // poles per block when staging: all of them while elements x tiles give
+    // >= 4096 blocks, else as many as keep ~4096 blocks
+    const long long et = (long long)I.n_leaf * hx::mm_tiles(I.nrhs, nt);
+    lu.pole_group = xl ? (int)std::max<long long>(1, std::min<long long>(I.npole, et * I.npole / 4096))
+                       : 1;
+    const long long npg = (I.npole + lu.pole_group - 1) / lu.pole_group;
+    // (the group's variant field carries the staging choice: instances in
+    // one fused launch share the kernel instantiation)
+    R.add(pass, O_LEAF_UP, 0, dbl ? K_LU_D : K_LU_F, nt, et * npg, lds, lu, HX_K_LEAF_UP, inst,
+          lu.x_lds);
 
     for (size_t l = 1; l < nl; ++l) {
       const Level& L = I.levels[l];
@@ -1581,8 +1598,8 @@ hipError_t launch_group(const hx_plan* plan, const Group& g, const unsigned char
   if (g.n == 1) return launch_one(blob, g, s);
   const int b = (int)g.blocks;
   switch (g.kind) {
-    case K_LU_D: return hx::launch_leaf_up_mm_multi<double>(multi_of<hx::MmLeafUpArgs<double>>(plan, g), b, g.nt, g.lds, s);
-    case K_LU_F: return hx::launch_leaf_up_mm_multi<float>(multi_of<hx::MmLeafUpArgs<float>>(plan, g), b, g.nt, g.lds, s);
+    case K_LU_D: return hx::launch_leaf_up_mm_multi<double>(multi_of<hx::MmLeafUpArgs<double>>(plan, g), b, g.nt, g.wv != 0, g.lds, s);
+    case K_LU_F: return hx::launch_leaf_up_mm_multi<float>(multi_of<hx::MmLeafUpArgs<float>>(plan, g), b, g.nt, g.wv != 0, g.lds, s);
     case K_MU_D: return hx::launch_merge_up_mm_multi<double>(multi_of<hx::MmMergeArgs<double>>(plan, g), b, g.nt, g.wv, s);
     case K_MU_F: return hx::launch_merge_up_mm_multi<float>(multi_of<hx::MmMergeArgs<float>>(plan, g), b, g.nt, g.wv, s);
     case K_MD_D: return hx::launch_merge_down_mm_multi<double>(multi_of<hx::MmMergeArgs<double>>(plan, g), b, g.nt, g.wv, s);
@@ -1643,15 +1660,20 @@ hx_status tune_instance(hx_plan* plan, Instance& I, int k, double* scratch, hipS
   for (int st = 0; st < HX_STAGES; ++st) {
     const int order = kTunedOrders[st];
     const bool merge = order == O_MERGE_UP || order == O_MERGE_DOWN;
-    std::vector<std::pair<int, int>> cand;   // (tiles, waves mode)
+    const bool up = order == O_LEAF_UP;
+    // (tiles, shape mode): merges 0 = level rule / 1 = one-wave blocks;
+    // upward elements 0 = stage the sources when they fit / 2 = never
+    std::vector<std::pair<int, int>> cand;
     for (int nt = 1; nt <= (I.nrhs > 16 ? 2 : 1); ++nt)
-      for (int wv = 0; wv <= (merge ? 1 : 0); ++wv) cand.push_back({nt, wv});
+      for (int v : (merge ? std::vector<int>{0, 1} : up ? std::vector<int>{0, 2} : std::vector<int>{0}))
+        cand.push_back({nt, v});
     if (cand.size() < 2) continue;
     float best = 1e30f;
     std::pair<int, int> best_c{0, 0};
     for (const auto& c : cand) {
       I.tune_nt[order] = I.nrhs > 16 ? c.first : 0;
-      I.tune_wv[order] = c.second;
+      if (merge) I.tune_wv[order] = c.second;
+      if (up) I.tune_xl = c.second;
       Recorder R;
       record_instance<T>(plan, I, k, scratch, R);
       Recorder one;
@@ -1680,7 +1702,8 @@ hx_status tune_instance(hx_plan* plan, Instance& I, int k, double* scratch, hipS
       }
     }
     I.tune_nt[order] = I.nrhs > 16 ? best_c.first : 0;
-    I.tune_wv[order] = best_c.second;
+    if (merge) I.tune_wv[order] = best_c.second;
+    if (up) I.tune_xl = best_c.second;
   }
   return HX_OK;
 }

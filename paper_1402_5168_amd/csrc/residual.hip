@@ -292,19 +292,6 @@ static hipError_t allow_residual_lds(size_t lds, bool multi) {
   return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-hipError_t launch_residual(const ResidualArgs& a0, int n_leaf, hipStream_t s) {
-  ResidualArgs a = a0;
-  a.RR = residual_rr(a);
-  const size_t lds = residual_lds_bytes(a.p, a.RR, a.nsrc);
-  const int nrg = (a.nrhs + a.RR - 1) / a.RR;
-  const bool sw = a.esum != nullptr;
-  const hipError_t e = sw ? allow_residual_lds<true>(lds, false) : allow_residual_lds<false>(lds, false);
-  if (e != hipSuccess) return e;
-  if (sw) hipLaunchKernelGGL(k_residual<true>, dim3(n_leaf * nrg), dim3(kBlock), lds, s, a);
-  else hipLaunchKernelGGL(k_residual<false>, dim3(n_leaf * nrg), dim3(kBlock), lds, s, a);
-  return hipGetLastError();
-}
-
 hipError_t launch_residual_one(const ResidualArgs& a, int blocks, bool sw, size_t lds, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   const hipError_t e = sw ? allow_residual_lds<true>(lds, false) : allow_residual_lds<false>(lds, false);

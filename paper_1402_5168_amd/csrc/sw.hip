@@ -246,16 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_sw_post_multi(Multi<SwPostArgs<T>> m
   sw_post_body<T>(a, bid);
 }
 
-hipError_t launch_sw_prep(const SwPrepArgs& a, int n_leaf, hipStream_t s) {
-  hipLaunchKernelGGL(k_sw_prep, dim3(n_leaf * a.nrhs), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
-}
 
-hipError_t launch_sw_wall(const SwWallArgs& a, hipStream_t s) {
-  const long long n = (long long)a.n_wall * a.nrhs;
-  hipLaunchKernelGGL(k_sw_wall, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
-}
 
 hipError_t launch_sw_root_form(const SwRootFormArgs& a, int chunk, hipStream_t s) {
   const long long nn = (long long)a.n * a.n;
@@ -275,15 +266,6 @@ int sw_post_rr(int p, int nrhs) {
 
 size_t sw_post_lds_bytes(int p, int RR) { return sizeof(double) * (size_t)p * p * (1 + 3 * (RR + 1)); }
 
-template <class T>
-hipError_t launch_sw_post(const SwPostArgs<T>& a0, int n_leaf, hipStream_t s) {
-  SwPostArgs<T> a = a0;
-  a.RR = sw_post_rr(a.p, a.nrhs);
-  const size_t lds = sw_post_lds_bytes(a.p, a.RR);
-  const int nrg = (a.nrhs + a.RR - 1) / a.RR;
-  hipLaunchKernelGGL((k_sw_post<T>), dim3(n_leaf * nrg), dim3(kBlock), lds, s, a);
-  return hipGetLastError();
-}
 
 template <class T>
 hipError_t launch_sw_post_multi(const Multi<SwPostArgs<T>>& m, int blocks, size_t lds, hipStream_t s) {
@@ -328,7 +310,5 @@ hipError_t launch_sw_wall_multi(const Multi<SwWallArgs>& m, int blocks, hipStrea
 template hipError_t launch_sw_post_multi<double>(const Multi<SwPostArgs<double>>&, int, size_t, hipStream_t);
 template hipError_t launch_sw_post_multi<float>(const Multi<SwPostArgs<float>>&, int, size_t, hipStream_t);
 
-template hipError_t launch_sw_post<double>(const SwPostArgs<double>&, int, hipStream_t);
-template hipError_t launch_sw_post<float>(const SwPostArgs<float>&, int, hipStream_t);
 
 }  // namespace hx
