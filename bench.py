@@ -178,7 +178,8 @@ def cpu_baseline(recipe, npole_folded: int, sub: int = 8, poles: int = 4,
             "step_seconds_sample": step_s}
 
 
-def run(w, precision: str, unbatched: bool, steps: int, warmup: int, profile: bool = True):
+def run(w, precision: str, unbatched: bool, steps: int, warmup: int, profile: bool = True,
+        autotune: bool = True):
     """Build one plan for the inputs w, time `steps` graph-replayed steps
     after `warmup` untimed ones, optionally profile the kernels.  Returns the
     measurements and the final state (host)."""
@@ -192,7 +193,9 @@ def run(w, precision: str, unbatched: bool, steps: int, warmup: int, profile: bo
     nrhs = w.state().shape[0]
     fp32 = precision == "fp32-refine"
     batched = fp32 or sw or (nrhs > 1 and not unbatched)
-    plan = hpsexp.Plan(device=0, flags=hpsexp.HX_FLAG_UNBATCHED if unbatched else 0,
+    flags = (hpsexp.HX_FLAG_UNBATCHED if unbatched else 0) | (
+        hpsexp.HX_FLAG_AUTOTUNE if autotune else 0)
+    plan = hpsexp.Plan(device=0, flags=flags,
                        precision=hpsexp.HX_FP32_REFINE if fp32 else hpsexp.HX_FP64)
     if sw:
         plan.add_sw(m.nex, m.ney, m.p, w.recipe.f, w.recipe.gH, w.tau, configs.DELTA,
@@ -229,12 +232,13 @@ def run(w, precision: str, unbatched: bool, steps: int, warmup: int, profile: bo
             kms, nl = plan.step_profile([state2], steps, stream=stream)
             del state2
     final = state.cpu().numpy()
+    tiles = plan.tiles(0)
     plan.close()
     del plan, state
     torch.cuda.empty_cache()
     ms_step = ms / max(steps, 1)
     out = {"value": info["dof_state"] * steps / (ms / 1e3), "ms_per_step": ms_step,
-           "build_s": build_s, "batched": batched, "info": info}
+           "build_s": build_s, "batched": batched, "info": info, "tiles": tiles}
     if profile:
         kernels = {}
         ab = algorithmic_bytes(m, info["folded_poles"], nrhs, sw)
@@ -418,7 +422,8 @@ def main():
     ap.add_argument("--max-instances", type=int, default=None,
                     help="batch workloads: at most this many instances")
     ap.add_argument("--autotune", type=int, default=1,
-                    help="batch workloads: tune the tile count per stage at build (1) or not (0)")
+                    help="tune the block shapes per stage at build (1, outside the timed region) "
+                         "or use the default rule (0)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device once (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -453,7 +458,8 @@ def main():
     m = w.mesh
     nrhs = w.state().shape[0]
     nfield = 3 if sw else 2
-    head, final = run(w, args.precision, args.unbatched, args.steps, args.warmup)
+    head, final = run(w, args.precision, args.unbatched, args.steps, args.warmup,
+                      autotune=bool(args.autotune))
     info = head["info"]
     out = {
         "metric": METRIC, "value": head["value"], "unit": "DOF·steps/s", "n_gpus": 1,
@@ -467,7 +473,8 @@ def main():
                    "precision": args.precision, "batched_rhs": head["batched"],
                    "tau": w.tau, "dof_state": info["dof_state"],
                    "dof_nodes": info["dof_nodes"], "fit_X": info["fit_X"],
-                   "max_abs_R": info["max_abs_R"],
+                   "max_abs_R": info["max_abs_R"], "autotune": bool(args.autotune),
+                   "tiles_per_stage": head["tiles"],
                    "operator_GiB": info["operator_bytes"] / 2 ** 30},
         "dof_nodes_steps_per_s": info["dof_nodes"] * args.steps * 1e3 /
                                  (head["ms_per_step"] * args.steps),
@@ -477,14 +484,16 @@ def main():
     }
     if not args.no_compare and args.precision == "fp32-refine":
         # the same inputs in FP64: batched, and one right-hand side
-        ref, ref_final = run(w, "fp64", False, args.steps, args.warmup, profile=False)
+        ref, ref_final = run(w, "fp64", False, args.steps, args.warmup, profile=False,
+                             autotune=bool(args.autotune))
         err = 0.0
         for r in range(nrhs):
             for f in range(nfield):
                 x, y = final[r, f], ref_final[r, f]
                 err = max(err, float(np.abs(x - y).max() / np.abs(y).max()))
         w1 = configs.make_sw(rec, n_rhs=1) if sw else configs.make(rec, n_rhs=1)
-        one, _ = run(w1, "fp64", False, max(args.steps // 2, 1), 1, profile=False)
+        one, _ = run(w1, "fp64", False, max(args.steps // 2, 1), 1, profile=False,
+                     autotune=bool(args.autotune))
         out["compare"] = {
             "rel_err_vs_fp64": err,
             "fp64_batched": {"value": ref["value"], "ms_per_step": ref["ms_per_step"]},

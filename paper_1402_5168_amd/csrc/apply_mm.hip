@@ -348,6 +348,22 @@ __device__ __forceinline__ void merge_up_body(const MmMergeArgs<T>& a, const int
   C* g3 = a.g3 + ((long long)pole * a.g3_pole + B.g3_off) * r;
   const C* Y = a.ops + pole * a.pole_stride + B.op_off + (long long)n3 * (ext + n3);
   const int row0 = rg * RB + (threadIdx.x >> 6) * 16;
+  const int lane = threadIdx.x & 63;
+  // the epilogue's base values (h1 of child a, h2 of child b) of this lane's
+  // output elements, loaded first so that their latency overlaps the
+  // staging and the products
+  C basev[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      basev[t][v].x = basev[t][v].y = T(0);
+      const int row = row0 + MM<T>::row(lane, v);
+      const int rhs = rt * RT + t * 16 + (lane & 15);
+      if (row < ext && rhs < r)
+        basev[t][v] = (row < n1) ? hc[(long long)(B.a_vec + i1[row]) * r + rhs]
+                                 : hc[(long long)(B.b_vec + i2[row - n1]) * r + rhs];
+    }
   Acc<T, NT> acc;
   acc.zero();
   for (int k0 = 0; k0 < n3; k0 += KC) {
@@ -382,16 +398,19 @@ __device__ __forceinline__ void merge_up_body(const MmMergeArgs<T>& a, const int
   }
   if (row0 >= ext) return;
   C* hp = a.self + ((long long)pole * a.self_pole + B.vec_off) * r;
-  mm_emit<T, NT>(acc, row0, ext, [&](int row, int j, C c) {
-    const int rhs = rt * RT + j;
-    if (rhs >= r) return;
-    const C base = (row < n1) ? hc[(long long)(B.a_vec + i1[row]) * r + rhs]
-                              : hc[(long long)(B.b_vec + i2[row - n1]) * r + rhs];
-    C o;
-    o.x = base.x - c.x;
-    o.y = base.y - c.y;
-    hp[(long long)row * r + rhs] = o;
-  });
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = row0 + MM<T>::row(lane, v);
+      const int rhs = rt * RT + t * 16 + (lane & 15);
+      if (row < ext && rhs < r) {
+        C o;
+        o.x = T(double(basev[t][v].x) - acc.vre(t, v));
+        o.y = T(double(basev[t][v].y) - acc.vim(t, v));
+        hp[(long long)row * r + rhs] = o;
+      }
+    }
 }
 
 template <class T, int NT, int WV = 4>
@@ -431,6 +450,16 @@ __device__ __forceinline__ void merge_down_body(const MmMergeArgs<T>& a, const i
   const C* up = a.self + ((long long)pole * a.self_pole + B.vec_off) * r;
   const C* g3 = a.g3 + ((long long)pole * a.g3_pole + B.g3_off) * r;
   C* uc = a.child + (long long)pole * a.child_pole * r;
+  const int row0 = rg * RB + (threadIdx.x >> 6) * 16;
+  const int lane = threadIdx.x & 63;
+  // child positions of this lane's output rows, fetched before the staging
+  int ia[4], ib[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = row0 + MM<T>::row(lane, v);
+    ia[v] = row < n3 ? i3a[row] : 0;
+    ib[v] = row < n3 ? i3b[row] : 0;
+  }
   if (rg == 0) {
     for (int idx = threadIdx.x; idx < ext * RT; idx += blockDim.x) {
       const int k = idx / RT, j = idx - k * RT;
@@ -442,7 +471,6 @@ __device__ __forceinline__ void merge_down_body(const MmMergeArgs<T>& a, const i
     }
   }
   const C* Z = a.ops + pole * a.pole_stride + B.op_off;
-  const int row0 = rg * RB + (threadIdx.x >> 6) * 16;
   Acc<T, NT> acc;
   acc.zero();
   for (int k0 = 0; k0 < m; k0 += KC) {
@@ -463,15 +491,20 @@ __device__ __forceinline__ void merge_down_body(const MmMergeArgs<T>& a, const i
     __syncthreads();
   }
   if (row0 >= n3) return;
-  mm_emit<T, NT>(acc, row0, n3, [&](int row, int j, C c) {
-    const int rhs = rt * RT + j;
-    if (rhs >= r) return;
-    C u3;
-    u3.x = -c.x;
-    u3.y = -c.y;
-    uc[(long long)(B.a_vec + i3a[row]) * r + rhs] = u3;
-    uc[(long long)(B.b_vec + i3b[row]) * r + rhs] = u3;
-  });
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = row0 + MM<T>::row(lane, v);
+      const int rhs = rt * RT + t * 16 + (lane & 15);
+      if (row < n3 && rhs < r) {
+        C u3;
+        u3.x = T(-acc.vre(t, v));
+        u3.y = T(-acc.vim(t, v));
+        uc[(long long)(B.a_vec + ia[v]) * r + rhs] = u3;
+        uc[(long long)(B.b_vec + ib[v]) * r + rhs] = u3;
+      }
+    }
 }
 
 template <class T, int NT, int WV = 4>
