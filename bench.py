@@ -42,25 +42,32 @@ TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_wave_64x64_p10_fp32refi
 TRAFFIC_SOURCES = ("apply_mm.hip", "hx_kernels.h", "hx_internal.h")
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch (read + written) of `kernel` from the committed
-    counter record of the default workload, or None when the record is
-    missing, is for another kernel, or the kernel sources changed since."""
+def measured_traffic(kernels):
+    """HBM bytes per launch of the upward element sweep, averaged over the
+    given kernel instantiations (one per launch of a step: the first sweep
+    and the correction sweep), from the committed counter record of the
+    default workload; None when the record is missing, lacks one of them,
+    or the kernel sources changed since it was taken."""
     import hashlib
     import re
 
     if not os.path.exists(TRAFFIC_RECORD):
         return None
-    m = re.search(r'traffic-record kernel="([^"]+)" fetch_bytes=(\d+) write_bytes=(\d+) '
-                  r'sources_sha256=([0-9a-f]+)', open(TRAFFIC_RECORD).read())
-    if not m or m.group(1) != kernel:
+    rec = {}
+    for m in re.finditer(r'traffic-record kernel="([^"]+)" fetch_bytes=(\d+) write_bytes=(\d+) '
+                         r'sources_sha256=([0-9a-f]+)', open(TRAFFIC_RECORD).read()):
+        rec[m.group(1)] = (int(m.group(2)), int(m.group(3)), m.group(4))
+    if not kernels or any(k not in rec for k in kernels):
         return None
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
         h.update(open(os.path.join(ROOT, "paper_1402_5168_amd", "csrc", f), "rb").read())
-    if h.hexdigest() != m.group(4):
+    if any(rec[k][2] != h.hexdigest() for k in kernels):
         return None
-    return {"read": int(m.group(2)), "written": int(m.group(3))}
+    n = len(kernels)
+    return {"read": sum(rec[k][0] for k in kernels) / n,
+            "written": sum(rec[k][1] for k in kernels) / n,
+            "per_launch": {k: {"read": rec[k][0], "written": rec[k][1]} for k in kernels}}
 
 
 def interface_nodes(mesh, walls: bool = False) -> int:
@@ -232,13 +239,14 @@ def run(w, precision: str, unbatched: bool, steps: int, warmup: int, profile: bo
             kms, nl = plan.step_profile([state2], steps, stream=stream)
             del state2
     final = state.cpu().numpy()
-    tiles = plan.tiles(0)
+    tiles, variants = plan.tiles(0), plan.variants(0)
     plan.close()
     del plan, state
     torch.cuda.empty_cache()
     ms_step = ms / max(steps, 1)
     out = {"value": info["dof_state"] * steps / (ms / 1e3), "ms_per_step": ms_step,
-           "build_s": build_s, "batched": batched, "info": info, "tiles": tiles}
+           "build_s": build_s, "batched": batched, "info": info, "tiles": tiles,
+           "variants": variants}
     if profile:
         kernels = {}
         ab = algorithmic_bytes(m, info["folded_poles"], nrhs, sw)
@@ -259,8 +267,14 @@ def run(w, precision: str, unbatched: bool, steps: int, warmup: int, profile: bo
             dom["flops_per_launch"] = flops
             dom["TFLOPs"] = tf
             peak = FP32_PEAK_TFLOPS if fp32 else FP64_PEAK_TFLOPS
-            tr = measured_traffic("hx::k_leaf_up_mm<float, 2>") if (
-                fp32 and not sw and w.recipe.name == "wave_64x64_p10" and nrhs == 32) else None
+            tr = None
+            if fp32 and not sw and w.recipe.name == "wave_64x64_p10" and nrhs == 32:
+                # the step's two upward sweeps: the first (sources staged or
+                # not, as tuned) and the correction sweep (never staged)
+                nt, staged = tiles[0], variants[0]
+                tr = measured_traffic([
+                    f"hx::k_leaf_up_mm<float, {nt}, {'true' if staged else 'false'}>",
+                    f"hx::k_leaf_up_mm<float, {nt}, false>"])
             out["roofline"] = {"bound": "mfma", "kernel": "k_leaf_up", "achieved": tf,
                                "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
                                "traffic": None if tr is None else tr["read"] + tr["written"],
@@ -474,7 +488,7 @@ def main():
                    "tau": w.tau, "dof_state": info["dof_state"],
                    "dof_nodes": info["dof_nodes"], "fit_X": info["fit_X"],
                    "max_abs_R": info["max_abs_R"], "autotune": bool(args.autotune),
-                   "tiles_per_stage": head["tiles"],
+                   "tiles_per_stage": head["tiles"], "variants_per_stage": head["variants"],
                    "operator_GiB": info["operator_bytes"] / 2 ** 30},
         "dof_nodes_steps_per_s": info["dof_nodes"] * args.steps * 1e3 /
                                  (head["ms_per_step"] * args.steps),

@@ -238,6 +238,19 @@ hx_status hx_step_profile(hx_plan* plan, double* const* states, int n_steps, voi
  * pass per right-hand side.  HX_EINVAL for a bad instance id. */
 hx_status hx_plan_tiles(const hx_plan* plan, int instance, int* tiles, int n);
 
+/* Kernel variants in use for instance `instance` (host array, first
+ * min(n, HX_STAGES) stages), chosen by the default rules or the autotuner:
+ *   HX_STAGE_LEAF_UP: 1 when the first upward sweep stages its source fields
+ *     in LDS once per block and walks a group of poles, 0 when every block
+ *     reads them for one pole;
+ *   HX_STAGE_MERGE_UP / HX_STAGE_MERGE_DOWN: 1 when every level runs
+ *     one-wave (16-row) blocks, 0 for the level rule (one wave where the
+ *     level's rows fit one 16-row tile, else four waves, 64 rows);
+ *   other stages: 0.
+ * All 0 for an instance that runs one pass per right-hand side.  Every
+ * variant gives bit-identical results.  HX_EINVAL for a bad instance id. */
+hx_status hx_plan_variants(const hx_plan* plan, int instance, int* variants, int n);
+
 /* Name of a status code. */
 const char* hx_status_str(int status);
 

@@ -1218,6 +1218,24 @@ int merge_wv(const Instance& I, int order, int rows) {
   return rows <= 16 ? 1 : 4;
 }
 
+// Tile count and source staging of the first upward element sweep: two
+// tiles only while g fits in 64 KiB; the sources are staged (and a group of
+// poles walked per block) while they fit beside g, unless the tuner chose
+// otherwise.  The correction sweep never stages (its sources differ per pole).
+struct LeafUpShape {
+  int nt;
+  bool staged;
+};
+
+template <class T>
+LeafUpShape leaf_up_shape(const Instance& I) {
+  const int nsrc = I.sw ? 3 : 2;
+  int nt = stage_nt(I, O_LEAF_UP);
+  if (nt == 2 && hx::leaf_up_lds_bytes<T>(I.q, 2, false, 0) > 65536) nt = 1;
+  const bool staged = I.tune_xl != 2 && hx::leaf_up_lds_bytes<T>(I.q, nt, false, nsrc) <= 65536;
+  return {nt, staged};
+}
+
 template <class T>
 void record_instance(const hx_plan* plan, const Instance& I, int inst, double* state, Recorder& R) {
   using C = typename hx::Cplx<T>::type;
@@ -1303,10 +1321,9 @@ void record_instance(const hx_plan* plan, const Instance& I, int inst, double* s
     // Staging the sources once per block and walking a group of poles pays
     // when the sources fit beside the staged g; otherwise one pole per block
     // reads them per pole (the tuner may also choose that on purpose).
-    int nt = stage_nt(I, O_LEAF_UP);
-    if (nt == 2 && hx::leaf_up_lds_bytes<T>(I.q, 2, false, 0) > 65536) nt = 1;
-    const bool xl = !pass && I.tune_xl != 2 &&
-                    hx::leaf_up_lds_bytes<T>(I.q, nt, false, lu.nsrc) <= 65536;
+    const LeafUpShape shape = leaf_up_shape<T>(I);
+    const int nt = shape.nt;
+    const bool xl = !pass && shape.staged;
     const int staged = xl ? lu.nsrc : 0;
     lu.x_lds = xl ? 1 : 0;
     lu.w_lds = hx::leaf_up_lds_bytes<T>(I.q, nt, true, staged) <= 65536 ? 1 : 0;
@@ -1937,6 +1954,26 @@ hx_status hx_plan_tiles(const hx_plan* plan, int instance, int* tiles, int n) {
   const Instance& I = plan->inst[instance];
   for (int st = 0; st < std::min(n, (int)HX_STAGES); ++st)
     tiles[st] = batched(plan, I) ? stage_nt(I, kTunedOrders[st]) : 0;
+  return HX_OK;
+}
+
+hx_status hx_plan_variants(const hx_plan* plan, int instance, int* variants, int n) {
+  g_last_error.clear();
+  if (!plan || !variants) return fail(HX_EINVAL, "null plan or variants");
+  if (instance < 0 || instance >= (int)plan->inst.size())
+    return fail(HX_EINVAL, "instance %d of %zu", instance, plan->inst.size());
+  const Instance& I = plan->inst[instance];
+  const bool b = batched(plan, I);
+  const bool f32 = I.fp32;
+  for (int st = 0; st < std::min(n, (int)HX_STAGES); ++st) {
+    const int order = kTunedOrders[st];
+    int v = 0;
+    if (b && st == HX_STAGE_LEAF_UP)
+      v = (f32 ? leaf_up_shape<float>(I) : leaf_up_shape<double>(I)).staged ? 1 : 0;
+    else if (b && (st == HX_STAGE_MERGE_UP || st == HX_STAGE_MERGE_DOWN))
+      v = I.tune_wv[order] == 1 ? 1 : 0;
+    variants[st] = v;
+  }
   return HX_OK;
 }
 

@@ -58,8 +58,8 @@ HX_STAGE_LEAF_UP, HX_STAGE_MERGE_UP, HX_STAGE_ROOT, HX_STAGE_MERGE_DOWN, HX_STAG
 HX_STAGES = 5
 
 EXPORTS = ("hx_plan_create", "hx_plan_add", "hx_plan_query", "hx_plan_bind",
-           "hx_plan_build", "hx_step", "hx_step_profile", "hx_plan_tiles", "hx_status_str",
-           "hx_last_error", "hx_plan_destroy")
+           "hx_plan_build", "hx_step", "hx_step_profile", "hx_plan_tiles", "hx_plan_variants",
+           "hx_status_str", "hx_last_error", "hx_plan_destroy")
 
 _lib = None
 
@@ -83,13 +83,14 @@ def load() -> ctypes.CDLL:
     lib.hx_step_profile.argtypes = [c_void_p, POINTER(c_void_p), c_int, c_void_p,
                                     POINTER(c_double), POINTER(c_int), c_int]
     lib.hx_plan_tiles.argtypes = [c_void_p, c_int, POINTER(c_int), c_int]
+    lib.hx_plan_variants.argtypes = [c_void_p, c_int, POINTER(c_int), c_int]
     lib.hx_status_str.argtypes = [c_int]
     lib.hx_status_str.restype = c_char_p
     lib.hx_last_error.argtypes = []
     lib.hx_last_error.restype = c_char_p
     lib.hx_plan_destroy.argtypes = [c_void_p]
     lib.hx_plan_destroy.restype = None
-    for name in EXPORTS[:8]:
+    for name in EXPORTS[:9]:
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -155,6 +156,12 @@ def hx_plan_tiles(plan, instance: int):
     t = (c_int * HX_STAGES)()
     _check(load().hx_plan_tiles(plan, instance, t, HX_STAGES))
     return list(t)
+
+
+def hx_plan_variants(plan, instance: int):
+    v = (c_int * HX_STAGES)()
+    _check(load().hx_plan_variants(plan, instance, v, HX_STAGES))
+    return list(v)
 
 
 def hx_status_str(status: int) -> str:
@@ -249,6 +256,11 @@ class Plan:
     def tiles(self, k: int):
         """Right-hand-side tiles per block of instance k, per HX_STAGE_*."""
         return hx_plan_tiles(self.handle, k)
+
+    def variants(self, k: int):
+        """Kernel variant per HX_STAGE_* of instance k (staged upward sweep,
+        one-wave merge blocks; 0 = the default shape)."""
+        return hx_plan_variants(self.handle, k)
 
     def step_profile(self, states, n_steps: int, stream=None):
         import torch

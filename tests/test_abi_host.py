@@ -166,6 +166,12 @@ def test_tile_counts_default_rule():
     assert plan.tiles(b) == [1] * hx.HX_STAGES
     assert plan.tiles(c) == [2] * hx.HX_STAGES
     assert status_of(lambda: plan.tiles(3)) == hx.HX_EINVAL
+    # default variants: small elements stage their sources; merges follow
+    # the level rule; an unbatched instance reports none
+    assert plan.variants(a) == [0] * hx.HX_STAGES
+    assert plan.variants(b) == [1, 0, 0, 0, 0]
+    assert plan.variants(c) == [1, 0, 0, 0, 0]
+    assert status_of(lambda: plan.variants(-1)) == hx.HX_EINVAL
     plan.close()
     assert status_of(lambda: hx.hx_plan_create(hx.HX_FP64, 0, 0x40)) == hx.HX_EINVAL
     hx.hx_plan_destroy(hx.hx_plan_create(hx.HX_FP64, 0, hx.HX_FLAG_AUTOTUNE))
