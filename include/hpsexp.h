@@ -101,8 +101,10 @@ typedef enum {
                                         instance's stages in each candidate
                                         shape (one or two right-hand-side
                                         tiles per block; merges also one-wave
-                                        blocks) and keeps the fastest
-                                        (hx_plan_tiles)                      */
+                                        blocks and pole groups; the upward
+                                        element sweep also source staging)
+                                        and keeps the fastest (hx_plan_tiles,
+                                        hx_plan_variants)                    */
 
 /* Mesh: [x0,x1] x [y0,y1] split into nex x ney equal elements, each with a
  * p x p Chebyshev-Lobatto grid (section 2.2).  nex and ney are powers of
@@ -243,9 +245,12 @@ hx_status hx_plan_tiles(const hx_plan* plan, int instance, int* tiles, int n);
  *   HX_STAGE_LEAF_UP: 1 when the first upward sweep stages its source fields
  *     in LDS once per block and walks a group of poles, 0 when every block
  *     reads them for one pole;
- *   HX_STAGE_MERGE_UP / HX_STAGE_MERGE_DOWN: 1 when every level runs
- *     one-wave (16-row) blocks, 0 for the level rule (one wave where the
- *     level's rows fit one 16-row tile, else four waves, 64 rows);
+ *   HX_STAGE_MERGE_UP / HX_STAGE_MERGE_DOWN: bit 0 set when every level
+ *     runs one-wave (16-row) blocks, clear for the level rule (one wave
+ *     where the level's rows fit one 16-row tile, else four waves, 64
+ *     rows); HX_STAGE_MERGE_UP also bit 1, set when every block serves
+ *     one pole, clear when the blocks of levels with many boxes walk a
+ *     group of poles;
  *   other stages: 0.
  * All 0 for an instance that runs one pass per right-hand side.  Every
  * variant gives bit-identical results.  HX_EINVAL for a bad instance id. */

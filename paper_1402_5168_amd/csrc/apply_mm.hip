@@ -84,17 +84,7 @@ struct Acc {
   }
 };
 
-// One wave: acc += A[its 16-row tile, columns k_lo .. k_lo+kc) * Bs[0..kc).
-// A points at row 0 of the operator; rows >= nrows and columns >= kc give 0
-// (no load is issued for them).  Bs holds kc rows rounded up to a multiple
-// of 4, zero-padded, with row stride bst.
-//
-// A complex tile product is four real MFMAs into two accumulators:
-//   re += a.re b.re,  im += a.re b.im,  re += (-a.im) b.im,  im += a.im b.re,
-// ordered so that the two MFMAs feeding one accumulator are not adjacent.
-// Each k-step of 4 columns needs one complex A entry per lane from HBM; a
-// ring of PF registers keeps the next PF k-steps' loads in flight while
-// the current MFMAs run, so a wave does not stall on HBM latency.
+// One complex k-step of 4 columns on a 16-row tile: acc += a * Bk.
 template <class T, int NT>
 __device__ __forceinline__ void mma_step(Acc<T, NT>& acc, const typename MM<T>::C a,
                                          const typename MM<T>::C* __restrict__ Bk) {
@@ -111,38 +101,61 @@ __device__ __forceinline__ void mma_step(Acc<T, NT>& acc, const typename MM<T>::
   }
 }
 
-template <class T, int NT>
-__device__ __forceinline__ void mm_chunk(Acc<T, NT>& acc, const typename MM<T>::C* __restrict__ A,
-                                         long long lda, int row0, int nrows, int k_lo, int kc,
-                                         const typename MM<T>::C* __restrict__ Bs, int bst) {
-  using C = typename MM<T>::C;
-  constexpr int PF = 8;
+// The A loads of one product chunk.  mm_prime issues the first PF k-steps'
+// loads; a caller may prime before it stages B, so that their latency
+// overlaps the staging, then mm_run consumes them.  Every lane issues every
+// load: a row past nrows reads the last row (its results are never
+// stored), a column past kc reads the last column (it meets a zero row of
+// B), and the loads past the chunk's end are never consumed.  With no
+// branch around them the compiler counts the loads in flight exactly, so
+// each k-step waits only for its own load, PF loads behind the newest.
+template <class T>
+struct ARing {
+  static constexpr int PF = 8;
+  typename MM<T>::C v[PF];
+  const typename MM<T>::C* ap;     // next load
+  const typename MM<T>::C* last;   // the lane's row, column kc - 1
+  long long step;
+  int kn;                          // column of the next load
+  int kc;
+};
+
+template <class T>
+__device__ __forceinline__ void mm_prime(ARing<T>& g, const typename MM<T>::C* __restrict__ A,
+                                         long long lda, int row0, int nrows, int k_lo, int kc) {
   const int lane = threadIdx.x & 63;
   const int i = lane & 15, kk = lane >> 4;
-  const bool rv = row0 + i < nrows;
-  const C* ap = A + row0 + i + (long long)(k_lo + kk) * lda;   // next load
-  const long long step = 4 * lda;
-  const int nsteps = (kc + 3) >> 2;
-  int kn = kk;                                                // column of the next load
-  C ring[PF];
+  const int row = min(row0 + i, nrows - 1);
+  g.ap = A + row + (long long)(k_lo + kk) * lda;
+  g.last = A + row + (long long)(k_lo + kc - 1) * lda;
+  g.step = 4 * lda;
+  g.kn = kk;
+  g.kc = kc;
 #pragma unroll
-  for (int u = 0; u < PF; ++u) {
-    ring[u].x = ring[u].y = T(0);
-    if (rv && kn < kc) ring[u] = ld_stream(ap);
-    ap += step;
-    kn += 4;
+  for (int u = 0; u < ARing<T>::PF; ++u) {
+    g.v[u] = ld_stream(g.kn < kc ? g.ap : g.last);
+    g.ap += g.step;
+    g.kn += 4;
   }
-  const C* Bk = Bs + kk * bst;
+}
+
+template <class T, int NT>
+__device__ __forceinline__ void mm_run(Acc<T, NT>& acc, ARing<T>& g,
+                                       const typename MM<T>::C* __restrict__ Bs, int bst) {
+  constexpr int PF = ARing<T>::PF;
+  const int kk = (threadIdx.x & 63) >> 4;
+  const int kc = g.kc;
+  const int nsteps = (kc + 3) >> 2;
+  const typename MM<T>::C* Bk = Bs + kk * bst;
   const int bstep = 4 * bst;
   int s0 = 0;
   for (; s0 + PF <= nsteps; s0 += PF) {
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
-      const C a = ring[u];
-      ring[u].x = ring[u].y = T(0);
-      if (rv && kn < kc) ring[u] = ld_stream(ap);
-      ap += step;
-      kn += 4;
+      const typename MM<T>::C a = g.v[u];
+      g.v[u] = ld_stream(g.kn < kc ? g.ap : g.last);
+      g.ap += g.step;
+      g.kn += 4;
       mma_step<T, NT>(acc, a, Bk);
       Bk += bstep;
     }
@@ -151,10 +164,43 @@ __device__ __forceinline__ void mm_chunk(Acc<T, NT>& acc, const typename MM<T>::
 #pragma unroll
   for (int u = 0; u < PF; ++u)
     if (s0 + u < nsteps) {
-      mma_step<T, NT>(acc, ring[u], Bk);
+      mma_step<T, NT>(acc, g.v[u], Bk);
       Bk += bstep;
     }
   acc.flush();
+}
+
+// One wave: acc += A[its 16-row tile, columns k_lo .. k_lo+kc) * Bs[0..kc).
+// A points at row 0 of the operator; rows >= nrows and columns >= kc give 0
+// (no load is issued for them).  Bs holds kc rows rounded up to a multiple
+// of 4, zero-padded, with row stride bst.
+//
+// A complex tile product is four real MFMAs into two accumulators:
+//   re += a.re b.re,  im += a.re b.im,  re += (-a.im) b.im,  im += a.im b.re,
+// ordered so that the two MFMAs feeding one accumulator are not adjacent.
+// Each k-step of 4 columns needs one complex A entry per lane from HBM; a
+// ring of PF registers keeps the next PF k-steps' loads in flight while
+// the current MFMAs run, so a wave does not stall on HBM latency.
+template <class T, int NT>
+__device__ __forceinline__ void mm_chunk(Acc<T, NT>& acc, const typename MM<T>::C* __restrict__ A,
+                                         long long lda, int row0, int nrows, int k_lo, int kc,
+                                         const typename MM<T>::C* __restrict__ Bs, int bst) {
+  ARing<T> g;
+  mm_prime(g, A, lda, row0, nrows, k_lo, kc);
+  mm_run<T, NT>(acc, g, Bs, bst);
+}
+
+// The dispatcher hands blocks to the eight XCDs in turn (block b to XCD
+// b mod 8), and each XCD has an L2 of its own.  Blocks that share an operand
+// (the row groups of one product share its B, the RHS tiles share its A) sit
+// at consecutive logical indices; this renumbering gives every XCD one
+// contiguous run of logical indices, taken in order, so that such blocks
+// meet in one L2 instead of each fetching the operand from HBM.  A bijection
+// of [0, gridDim.x) for any grid size.
+__device__ __forceinline__ int xcd_block() {
+  const int b = blockIdx.x, n = gridDim.x;
+  const int x = b & 7, s = b >> 3, q = n >> 3, rm = n & 7;
+  return x < rm ? x * (q + 1) + s : rm * (q + 1) + (x - rm) * q + s;
 }
 
 // Visit the wave's results: f(row, j, value) for row < nrows, j < RT.
@@ -311,13 +357,13 @@ __device__ __forceinline__ void leaf_up_body(const MmLeafUpArgs<T>& a, const int
 
 template <class T, int NT, bool XL>
 __global__ __launch_bounds__(kBlock) void k_leaf_up_mm(MmLeafUpArgs<T> a) {
-  leaf_up_body<T, NT, XL>(a, blockIdx.x);
+  leaf_up_body<T, NT, XL>(a, xcd_block());
 }
 
 template <class T, int NT, bool XL>
 __global__ __launch_bounds__(kBlock) void k_leaf_up_mm_multi(Multi<MmLeafUpArgs<T>> m) {
   int i;
-  const int bid = m.locate(blockIdx.x, i);
+  const int bid = m.locate(xcd_block(), i);
   const MmLeafUpArgs<T> a = m.args[i];
   leaf_up_body<T, NT, XL>(a, bid);
 }
@@ -331,11 +377,12 @@ __device__ __forceinline__ void merge_up_body(const MmMergeArgs<T>& a, const int
   constexpr int RB = 16 * WV, KC = WV == 4 ? kKC : 32;  // rows per block, k-chunk
   __shared__ C Bs[KC * BST];
   const int n_rt = (a.nrhs + RT - 1) / RT;
+  const int G = a.pole_group, npg = (a.npole + G - 1) / G;
   int rest = bid;
   const int rg = rest % a.row_groups; rest /= a.row_groups;
   const int rt = rest % n_rt; rest /= n_rt;
-  const int pole = rest % a.npole;
-  const int box = rest / a.npole;
+  const int pg = rest % npg;
+  const int box = rest / npg;
   const BoxDesc B = a.boxes[box];
   const int n1 = B.n1, n2 = B.n2, n3 = B.n3, ext = n1 + n2;
   if (rg > 0 && rg * RB >= ext) return;
@@ -343,85 +390,98 @@ __device__ __forceinline__ void merge_up_body(const MmMergeArgs<T>& a, const int
   const int* i2 = i1 + n1;
   const int* i3a = i2 + n2;
   const int* i3b = i3a + n3;
+  const int* ja = a.idx + B.j_off;
   const int r = a.nrhs;
-  const C* hc = a.child + (long long)pole * a.child_pole * r;
-  C* g3 = a.g3 + ((long long)pole * a.g3_pole + B.g3_off) * r;
-  const C* Y = a.ops + pole * a.pole_stride + B.op_off + (long long)n3 * (ext + n3);
   const int row0 = rg * RB + (threadIdx.x >> 6) * 16;
   const int lane = threadIdx.x & 63;
-  // the epilogue's base values (h1 of child a, h2 of child b) of this lane's
-  // output elements, loaded first so that their latency overlaps the
-  // staging and the products
-  C basev[NT][4];
+  // child vector positions of this lane's output rows (h1 of child a, h2 of
+  // child b), the same for every pole
+  int bo[4];
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      basev[t][v].x = basev[t][v].y = T(0);
-      const int row = row0 + MM<T>::row(lane, v);
-      const int rhs = rt * RT + t * 16 + (lane & 15);
-      if (row < ext && rhs < r)
-        basev[t][v] = (row < n1) ? hc[(long long)(B.a_vec + i1[row]) * r + rhs]
-                                 : hc[(long long)(B.b_vec + i2[row - n1]) * r + rhs];
-    }
-  Acc<T, NT> acc;
-  acc.zero();
-  for (int k0 = 0; k0 < n3; k0 += KC) {
-    const int kc = min(KC, n3 - k0), kcp = (kc + 3) & ~3;
-    for (int idx = threadIdx.x; idx < kcp * RT; idx += blockDim.x) {
-      const int k = idx / RT, j = idx - k * RT;
-      const int rhs = rt * RT + j;
-      C v;
-      v.x = v.y = T(0);
-      if (k < kc && rhs < r) {
-        const C x = hc[(long long)(B.a_vec + i3a[k0 + k]) * r + rhs];
-        const C y = hc[(long long)(B.b_vec + i3b[k0 + k]) * r + rhs];
-        v.x = x.x + y.x;
-        v.y = x.y + y.y;
-        if (a.dn) {
-          // flux rows of the correction: du/dn(a) + du/dn(b) = -(dn_a + dn_b),
-          // which enters as g3 = h3a + h3b + dn_a + dn_b
-          const int* ja = a.idx + B.j_off;
-          const double2* dp = a.dn + (long long)pole * a.dn_pole * r;
-          const double2 da = dp[(long long)ja[k0 + k] * r + rhs];
-          const double2 db = dp[(long long)ja[n3 + k0 + k] * r + rhs];
-          v.x += T(da.x + db.x);
-          v.y += T(da.y + db.y);
-        }
-        if (rg == 0) g3[(long long)(k0 + k) * r + rhs] = v;
-      }
-      Bs[k * BST + j] = v;
-    }
-    __syncthreads();
-    if (row0 < ext) mm_chunk<T, NT>(acc, Y, ext, row0, ext, k0, kc, Bs, BST);
-    __syncthreads();
+  for (int v = 0; v < 4; ++v) {
+    const int row = row0 + MM<T>::row(lane, v);
+    bo[v] = row >= ext ? 0 : row < n1 ? B.a_vec + i1[row] : B.b_vec + i2[row - n1];
   }
-  if (row0 >= ext) return;
-  C* hp = a.self + ((long long)pole * a.self_pole + B.vec_off) * r;
+  const int p_end = min(a.npole, (pg + 1) * G);
+  for (int pole = pg * G; pole < p_end; ++pole) {
+    const C* hc = a.child + (long long)pole * a.child_pole * r;
+    C* g3 = a.g3 + ((long long)pole * a.g3_pole + B.g3_off) * r;
+    const C* Y = a.ops + pole * a.pole_stride + B.op_off + (long long)n3 * (ext + n3);
+    // the epilogue's base values, loaded first so that their latency
+    // overlaps the staging and the products
+    C basev[NT][4];
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = row0 + MM<T>::row(lane, v);
-      const int rhs = rt * RT + t * 16 + (lane & 15);
-      if (row < ext && rhs < r) {
-        C o;
-        o.x = T(double(basev[t][v].x) - acc.vre(t, v));
-        o.y = T(double(basev[t][v].y) - acc.vim(t, v));
-        hp[(long long)row * r + rhs] = o;
+      for (int v = 0; v < 4; ++v) {
+        basev[t][v].x = basev[t][v].y = T(0);
+        const int row = row0 + MM<T>::row(lane, v);
+        const int rhs = rt * RT + t * 16 + (lane & 15);
+        if (row < ext && rhs < r) basev[t][v] = hc[(long long)bo[v] * r + rhs];
       }
+    Acc<T, NT> acc;
+    acc.zero();
+    // each chunk's operator loads are issued before its B is staged
+    ARing<T> ring;
+    if (row0 < ext) mm_prime(ring, Y, ext, row0, ext, 0, min(KC, n3));
+    for (int k0 = 0; k0 < n3; k0 += KC) {
+      const int kc = min(KC, n3 - k0), kcp = (kc + 3) & ~3;
+      for (int idx = threadIdx.x; idx < kcp * RT; idx += blockDim.x) {
+        const int k = idx / RT, j = idx - k * RT;
+        const int rhs = rt * RT + j;
+        C v;
+        v.x = v.y = T(0);
+        if (k < kc && rhs < r) {
+          const C x = hc[(long long)(B.a_vec + i3a[k0 + k]) * r + rhs];
+          const C y = hc[(long long)(B.b_vec + i3b[k0 + k]) * r + rhs];
+          v.x = x.x + y.x;
+          v.y = x.y + y.y;
+          if (a.dn) {
+            // flux rows of the correction: du/dn(a) + du/dn(b) = -(dn_a + dn_b),
+            // which enters as g3 = h3a + h3b + dn_a + dn_b
+            const double2* dp = a.dn + (long long)pole * a.dn_pole * r;
+            const double2 da = dp[(long long)ja[k0 + k] * r + rhs];
+            const double2 db = dp[(long long)ja[n3 + k0 + k] * r + rhs];
+            v.x += T(da.x + db.x);
+            v.y += T(da.y + db.y);
+          }
+          if (rg == 0) g3[(long long)(k0 + k) * r + rhs] = v;
+        }
+        Bs[k * BST + j] = v;
+      }
+      __syncthreads();
+      if (row0 < ext) mm_run<T, NT>(acc, ring, Bs, BST);
+      __syncthreads();
+      if (row0 < ext && k0 + KC < n3) mm_prime(ring, Y, ext, row0, ext, k0 + KC, min(KC, n3 - k0 - KC));
     }
+    if (row0 < ext) {
+      C* hp = a.self + ((long long)pole * a.self_pole + B.vec_off) * r;
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = row0 + MM<T>::row(lane, v);
+          const int rhs = rt * RT + t * 16 + (lane & 15);
+          if (row < ext && rhs < r) {
+            C o;
+            o.x = T(double(basev[t][v].x) - acc.vre(t, v));
+            o.y = T(double(basev[t][v].y) - acc.vim(t, v));
+            hp[(long long)row * r + rhs] = o;
+          }
+        }
+    }
+  }
 }
 
 template <class T, int NT, int WV = 4>
 __global__ __launch_bounds__(64 * WV) void k_merge_up_mm(MmMergeArgs<T> a) {
-  merge_up_body<T, NT, WV>(a, blockIdx.x);
+  merge_up_body<T, NT, WV>(a, xcd_block());
 }
 
 template <class T, int NT, int WV = 4>
 __global__ __launch_bounds__(64 * WV) void k_merge_up_mm_multi(Multi<MmMergeArgs<T>> m) {
   int i;
-  const int bid = m.locate(blockIdx.x, i);
+  const int bid = m.locate(xcd_block(), i);
   const MmMergeArgs<T> a = m.args[i];
   merge_up_body<T, NT, WV>(a, bid);
 }
@@ -470,7 +530,10 @@ __device__ __forceinline__ void merge_down_body(const MmMergeArgs<T>& a, const i
       else uc[(long long)(B.b_vec + i2[k - n1]) * r + rhs] = v;
     }
   }
+  // each chunk's operator loads are issued before its B is staged
   const C* Z = a.ops + pole * a.pole_stride + B.op_off;
+  ARing<T> ring;
+  if (row0 < n3) mm_prime(ring, Z, n3, row0, n3, 0, min(KC, m));
   Acc<T, NT> acc;
   acc.zero();
   for (int k0 = 0; k0 < m; k0 += KC) {
@@ -487,8 +550,9 @@ __device__ __forceinline__ void merge_down_body(const MmMergeArgs<T>& a, const i
       Bs[k * BST + j] = v;
     }
     __syncthreads();
-    if (row0 < n3) mm_chunk<T, NT>(acc, Z, n3, row0, n3, k0, kc, Bs, BST);
+    if (row0 < n3) mm_run<T, NT>(acc, ring, Bs, BST);
     __syncthreads();
+    if (row0 < n3 && k0 + KC < m) mm_prime(ring, Z, n3, row0, n3, k0 + KC, min(KC, m - k0 - KC));
   }
   if (row0 >= n3) return;
 #pragma unroll
@@ -509,13 +573,13 @@ __device__ __forceinline__ void merge_down_body(const MmMergeArgs<T>& a, const i
 
 template <class T, int NT, int WV = 4>
 __global__ __launch_bounds__(64 * WV) void k_merge_down_mm(MmMergeArgs<T> a) {
-  merge_down_body<T, NT, WV>(a, blockIdx.x);
+  merge_down_body<T, NT, WV>(a, xcd_block());
 }
 
 template <class T, int NT, int WV = 4>
 __global__ __launch_bounds__(64 * WV) void k_merge_down_mm_multi(Multi<MmMergeArgs<T>> m) {
   int i;
-  const int bid = m.locate(blockIdx.x, i);
+  const int bid = m.locate(xcd_block(), i);
   const MmMergeArgs<T> a = m.args[i];
   merge_down_body<T, NT, WV>(a, bid);
 }
@@ -537,6 +601,25 @@ __device__ __forceinline__ void leaf_down_body(const MmLeafDownArgs<T>& a, const
   const LeafDesc L = a.leaves[leaf];
   const int r = a.nrhs, e = L.e, ep = (e + 3) & ~3;
   const C* ue = a.u + ((long long)pole * a.u_pole + L.vec_off) * r;
+  const int row0 = rg * 64 + (threadIdx.x >> 6) * 16;
+  const int lane = threadIdx.x & 63;
+  const C* S = a.ops + pole * a.pole_stride + L.op_off + (long long)q2 * q2;
+  C* w = a.w + ((long long)pole * a.w_pole + (long long)leaf * q2) * r;
+  C* yo = a.y0 ? a.y0 + ((long long)pole * a.w_pole + (long long)leaf * q2) * r : w;
+  // this lane's w entries and the operator loads are issued before the
+  // staging, so that the block waits for memory once
+  C wv[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = row0 + MM<T>::row(lane, v);
+      const int rhs = rt * RT + t * 16 + (lane & 15);
+      wv[t][v].x = wv[t][v].y = T(0);
+      if (row < q2 && rhs < r) wv[t][v] = w[(long long)row * r + rhs];
+    }
+  ARing<T> ring;
+  if (row0 < q2 && e > 0) mm_prime(ring, S, q2, row0, q2, 0, e);
   for (int idx = threadIdx.x; idx < ep * RT; idx += blockDim.x) {
     const int k = idx / RT, j = idx - k * RT;
     const int rhs = rt * RT + j;
@@ -546,33 +629,34 @@ __device__ __forceinline__ void leaf_down_body(const MmLeafDownArgs<T>& a, const
     Bs[k * BST + j] = v;
   }
   __syncthreads();
-  const int row0 = rg * 64 + (threadIdx.x >> 6) * 16;
   if (row0 >= q2) return;
-  const C* S = a.ops + pole * a.pole_stride + L.op_off + (long long)q2 * q2;
   Acc<T, NT> acc;
   acc.zero();
-  if (e > 0) mm_chunk<T, NT>(acc, S, q2, row0, q2, 0, e, Bs, BST);
-  C* w = a.w + ((long long)pole * a.w_pole + (long long)leaf * q2) * r;
-  C* yo = a.y0 ? a.y0 + ((long long)pole * a.w_pole + (long long)leaf * q2) * r : w;
-  mm_emit<T, NT>(acc, row0, q2, [&](int row, int j, C c) {
-    const int rhs = rt * RT + j;
-    if (rhs >= r) return;
-    C o = w[(long long)row * r + rhs];
-    o.x -= c.x;
-    o.y -= c.y;
-    yo[(long long)row * r + rhs] = o;
-  });
+  if (e > 0) mm_run<T, NT>(acc, ring, Bs, BST);
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = row0 + MM<T>::row(lane, v);
+      const int rhs = rt * RT + t * 16 + (lane & 15);
+      if (row < q2 && rhs < r) {
+        C o = wv[t][v];
+        o.x -= T(acc.vre(t, v));
+        o.y -= T(acc.vim(t, v));
+        yo[(long long)row * r + rhs] = o;
+      }
+    }
 }
 
 template <class T, int NT>
 __global__ __launch_bounds__(kBlock) void k_leaf_down_mm(MmLeafDownArgs<T> a) {
-  leaf_down_body<T, NT>(a, blockIdx.x);
+  leaf_down_body<T, NT>(a, xcd_block());
 }
 
 template <class T, int NT>
 __global__ __launch_bounds__(kBlock) void k_leaf_down_mm_multi(Multi<MmLeafDownArgs<T>> m) {
   int i;
-  const int bid = m.locate(blockIdx.x, i);
+  const int bid = m.locate(xcd_block(), i);
   const MmLeafDownArgs<T> a = m.args[i];
   leaf_down_body<T, NT>(a, bid);
 }
@@ -601,6 +685,28 @@ __device__ __forceinline__ void leaf_down_sum_body(const MmLeafDownArgs<T>& a, c
     for (int v = 0; v < 4; ++v) su[t][v] = sv[t][v] = 0.0;
   for (int pole = 0; pole < a.npole; ++pole) {
     const C* ue = a.u + ((long long)pole * a.u_pole + L.vec_off) * r;
+    const C* S = a.ops + pole * a.pole_stride + L.op_off + (long long)q2 * q2;
+    const C* w = a.w + ((long long)pole * a.w_pole + (long long)leaf * q2) * r;
+    const C* y0 = a.y0 ? a.y0 + ((long long)pole * a.w_pole + (long long)leaf * q2) * r : nullptr;
+    // this pole's w (and first-sweep y) entries of the lane and its operator
+    // loads are issued before the staging: one wait for memory per pole
+    C wv[NT][4], y0v[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = row0 + MM<T>::row(lane, v);
+        const int rhs = rt * RT + t * 16 + (lane & 15);
+        wv[t][v].x = wv[t][v].y = T(0);
+        y0v[t][v].x = y0v[t][v].y = T(0);
+        if (row < q2 && rhs < r) {
+          wv[t][v] = w[(long long)row * r + rhs];
+          // corrected solution of the precision form: y0 + (w - S u_e)
+          if (y0) y0v[t][v] = y0[(long long)row * r + rhs];
+        }
+      }
+    ARing<T> ring;
+    if (row0 < q2 && e > 0) mm_prime(ring, S, q2, row0, q2, 0, e);
     for (int idx = threadIdx.x; idx < ep * RT; idx += blockDim.x) {
       const int k = idx / RT, j = idx - k * RT;
       const int rhs = rt * RT + j;
@@ -611,12 +717,9 @@ __device__ __forceinline__ void leaf_down_sum_body(const MmLeafDownArgs<T>& a, c
     }
     __syncthreads();
     if (row0 < q2) {
-      const C* S = a.ops + pole * a.pole_stride + L.op_off + (long long)q2 * q2;
       Acc<T, NT> acc;
       acc.zero();
-      if (e > 0) mm_chunk<T, NT>(acc, S, q2, row0, q2, 0, e, Bs, BST);
-      const C* w = a.w + ((long long)pole * a.w_pole + (long long)leaf * q2) * r;
-      const C* y0 = a.y0 ? a.y0 + ((long long)pole * a.w_pole + (long long)leaf * q2) * r : nullptr;
+      if (e > 0) mm_run<T, NT>(acc, ring, Bs, BST);
       const PoleCoef pc = a.coef[pole];
 #pragma unroll
       for (int t = 0; t < NT; ++t)
@@ -625,13 +728,11 @@ __device__ __forceinline__ void leaf_down_sum_body(const MmLeafDownArgs<T>& a, c
           const int row = row0 + MM<T>::row(lane, v);
           const int rhs = rt * RT + t * 16 + (lane & 15);
           if (row < q2 && rhs < r) {
-            const C wv = w[(long long)row * r + rhs];
-            double yr = double(wv.x) - acc.vre(t, v);
-            double yi = double(wv.y) - acc.vim(t, v);
-            if (y0) {  // corrected solution of the precision form
-              const C y0v = y0[(long long)row * r + rhs];
-              yr += double(y0v.x);
-              yi += double(y0v.y);
+            double yr = double(wv[t][v].x) - acc.vre(t, v);
+            double yi = double(wv[t][v].y) - acc.vim(t, v);
+            if (y0) {
+              yr += double(y0v[t][v].x);
+              yi += double(y0v[t][v].y);
             }
             su[t][v] = fma(pc.cu.x, yr, fma(-pc.cu.y, yi, su[t][v]));
             sv[t][v] = fma(pc.cv.x, yr, fma(-pc.cv.y, yi, sv[t][v]));
@@ -658,13 +759,13 @@ __device__ __forceinline__ void leaf_down_sum_body(const MmLeafDownArgs<T>& a, c
 
 template <class T, int NT>
 __global__ __launch_bounds__(kBlock) void k_leaf_down_sum_mm(MmLeafDownArgs<T> a) {
-  leaf_down_sum_body<T, NT>(a, blockIdx.x);
+  leaf_down_sum_body<T, NT>(a, xcd_block());
 }
 
 template <class T, int NT>
 __global__ __launch_bounds__(kBlock) void k_leaf_down_sum_mm_multi(Multi<MmLeafDownArgs<T>> m) {
   int i;
-  const int bid = m.locate(blockIdx.x, i);
+  const int bid = m.locate(xcd_block(), i);
   const MmLeafDownArgs<T> a = m.args[i];
   leaf_down_sum_body<T, NT>(a, bid);
 }
@@ -730,13 +831,13 @@ __device__ __forceinline__ void sw_root_body(const SwRootArgs<T>& a, const int b
 
 template <class T, int NT>
 __global__ __launch_bounds__(kBlock) void k_sw_root_mm(SwRootArgs<T> a) {
-  sw_root_body<T, NT>(a, blockIdx.x);
+  sw_root_body<T, NT>(a, xcd_block());
 }
 
 template <class T, int NT>
 __global__ __launch_bounds__(kBlock) void k_sw_root_mm_multi(Multi<SwRootArgs<T>> m) {
   int i;
-  const int bid = m.locate(blockIdx.x, i);
+  const int bid = m.locate(xcd_block(), i);
   const SwRootArgs<T> a = m.args[i];
   sw_root_body<T, NT>(a, bid);
 }

@@ -144,6 +144,9 @@ struct MmMergeArgs {
   // elements' values nearly cancel (null: none)
   const double2* dn;
   long long dn_pole;
+  // upward pass: poles per block (>= 1); a block walks poles
+  // [g G, (g + 1) G) of its box, row group and RHS tile (downward: 1)
+  int pole_group;
 };
 
 template <class T>

@@ -112,6 +112,7 @@ struct Instance {
   int tune_nt[8] = {0, 0, 0, 0, 0, 0, 0, 0}; // per stage: right-hand-side tiles (0: default)
   int tune_wv[8] = {0, 0, 0, 0, 0, 0, 0, 0}; // merge stages: 1 = one-wave blocks at every level
   int tune_xl = 0;                          // upward elements: 2 = never stage the sources
+  int tune_pg[8] = {0, 0, 0, 0, 0, 0, 0, 0}; // merge stages: 1 = one pole per block
   bool fp32 = false;                        // precision form: FP32 operators and sweeps
   // shallow water: wall nodes are exterior unknowns up to the root
   bool sw = false;
@@ -1218,6 +1219,17 @@ int merge_wv(const Instance& I, int order, int rows) {
   return rows <= 16 ? 1 : 4;
 }
 
+// Poles per block of an upward merge level whose launch would have `blocks` blocks
+// with one pole each: as many as keep about kMergeBlocks blocks (one pole
+// per block for levels with fewer), unless the tuner chose one pole per
+// block.  A block then pays its descriptor and index loads once for the
+// whole group.
+constexpr long long kMergeBlocks = 16384;
+int merge_pole_group(const Instance& I, int order, long long blocks) {
+  if (I.tune_pg[order] == 1) return 1;
+  return (int)std::max<long long>(1, std::min<long long>(I.npole, blocks / kMergeBlocks));
+}
+
 // Tile count and source staging of the first upward element sweep: two
 // tiles only while g fits in 64 KiB; the sources are staged (and a group of
 // poles walked per block) while they fit beside g, unless the tuner chose
@@ -1359,9 +1371,10 @@ void record_instance(const hx_plan* plan, const Instance& I, int inst, double* s
       m.dn = pass ? dn : nullptr;
       m.dn_pole = I.levels[0].total_ext;
       const int mnt = stage_nt(I, O_MERGE_UP);
+      const long long per_pole = (long long)L.boxes.size() * hx::mm_tiles(I.nrhs, mnt) * m.row_groups;
+      m.pole_group = merge_pole_group(I, O_MERGE_UP, per_pole * I.npole);
       R.add(pass, O_MERGE_UP, (int)l, dbl ? K_MU_D : K_MU_F, mnt,
-            (long long)L.boxes.size() * I.npole * hx::mm_tiles(I.nrhs, mnt) * m.row_groups, 0, m,
-            HX_K_MERGE_UP, inst, wv);
+            per_pole * ((I.npole + m.pole_group - 1) / m.pole_group), 0, m, HX_K_MERGE_UP, inst, wv);
     }
     if (sw) {
       const Level& Rt = I.levels[nl - 1];
@@ -1405,6 +1418,7 @@ void record_instance(const hx_plan* plan, const Instance& I, int inst, double* s
       m.g3 = vec(L.d_g3);
       m.g3_pole = L.total_n3;
       const int mnt = stage_nt(I, O_MERGE_DOWN);
+      m.pole_group = 1;   // one pole per block (the downward kernel has no pole loop)
       R.add(pass, O_MERGE_DOWN, -(int)l, dbl ? K_MD_D : K_MD_F, mnt,
             (long long)L.boxes.size() * I.npole * hx::mm_tiles(I.nrhs, mnt) * m.row_groups, 0, m,
             HX_K_MERGE_DOWN, inst, wv);
@@ -1670,7 +1684,9 @@ constexpr int kTunedOrders[HX_STAGES] = {O_LEAF_UP, O_MERGE_UP, O_ROOT, O_MERGE_
 // scratch state in the build workspace, time the best of three runs of
 // each, keep the fastest.  Candidates: 1 or 2 right-hand-side tiles per
 // block (more than 16 right-hand sides only); for the merge stages also
-// one-wave blocks at every level against the level rule of merge_wv.
+// one-wave blocks at every level against the level rule of merge_wv, and
+// one pole per block against the pole groups of merge_pole_group; for the
+// upward element sweep, staged sources against none.
 template <class T>
 hx_status tune_instance(hx_plan* plan, Instance& I, int k, double* scratch, hipStream_t s,
                         hipEvent_t e0, hipEvent_t e1) {
@@ -1678,18 +1694,25 @@ hx_status tune_instance(hx_plan* plan, Instance& I, int k, double* scratch, hipS
     const int order = kTunedOrders[st];
     const bool merge = order == O_MERGE_UP || order == O_MERGE_DOWN;
     const bool up = order == O_LEAF_UP;
-    // (tiles, shape mode): merges 0 = level rule / 1 = one-wave blocks;
+    // (tiles, shape mode): merges bit 0 = one-wave blocks (else the level
+    // rule), upward merges bit 1 = one pole per block (else pole groups);
     // upward elements 0 = stage the sources when they fit / 2 = never
     std::vector<std::pair<int, int>> cand;
     for (int nt = 1; nt <= (I.nrhs > 16 ? 2 : 1); ++nt)
-      for (int v : (merge ? std::vector<int>{0, 1} : up ? std::vector<int>{0, 2} : std::vector<int>{0}))
+      for (int v : (order == O_MERGE_UP     ? std::vector<int>{0, 1, 2, 3}
+                    : order == O_MERGE_DOWN ? std::vector<int>{0, 1}
+                    : up                    ? std::vector<int>{0, 2}
+                                            : std::vector<int>{0}))
         cand.push_back({nt, v});
     if (cand.size() < 2) continue;
     float best = 1e30f;
     std::pair<int, int> best_c{0, 0};
     for (const auto& c : cand) {
       I.tune_nt[order] = I.nrhs > 16 ? c.first : 0;
-      if (merge) I.tune_wv[order] = c.second;
+      if (merge) {
+        I.tune_wv[order] = c.second & 1;
+        I.tune_pg[order] = (c.second >> 1) & 1;
+      }
       if (up) I.tune_xl = c.second;
       Recorder R;
       record_instance<T>(plan, I, k, scratch, R);
@@ -1719,7 +1742,10 @@ hx_status tune_instance(hx_plan* plan, Instance& I, int k, double* scratch, hipS
       }
     }
     I.tune_nt[order] = I.nrhs > 16 ? best_c.first : 0;
-    if (merge) I.tune_wv[order] = best_c.second;
+    if (merge) {
+      I.tune_wv[order] = best_c.second & 1;
+      I.tune_pg[order] = (best_c.second >> 1) & 1;
+    }
     if (up) I.tune_xl = best_c.second;
   }
   return HX_OK;
@@ -1971,7 +1997,7 @@ hx_status hx_plan_variants(const hx_plan* plan, int instance, int* variants, int
     if (b && st == HX_STAGE_LEAF_UP)
       v = (f32 ? leaf_up_shape<float>(I) : leaf_up_shape<double>(I)).staged ? 1 : 0;
     else if (b && (st == HX_STAGE_MERGE_UP || st == HX_STAGE_MERGE_DOWN))
-      v = I.tune_wv[order] == 1 ? 1 : 0;
+      v = (I.tune_wv[order] == 1 ? 1 : 0) | (I.tune_pg[order] == 1 ? 2 : 0);
     variants[st] = v;
   }
   return HX_OK;
