@@ -35,14 +35,18 @@ __device__ __forceinline__ int side_of_slot_r(int mask, int slot) {
   return -1;
 }
 
+// Threads per block and grid items per thread: RR p^2 <= kPer kResBlock.
+constexpr int kResBlock = 512;
+constexpr int kPer = 4;
+
 template <bool SW>
 __device__ __forceinline__ void residual_body(const ResidualArgs& a, const int bid) {
   const int RR = a.RR;
   // Work items are rhs-fastest (RR is a power of two).  Each thread fetches
-  // the same kPer grid items (node, rhs) for every pole (RR p^2 <= kPer
-  // kBlock), with offsets computed once; the interior rows and edge slots
-  // look their node indices up in small LDS tables.
-  constexpr int kPer = 8;
+  // the same kPer grid items (node, rhs) for every pole, with offsets
+  // computed once; the interior rows and edge slots look their node indices
+  // up in small LDS tables.  The grid values are FP32 (as the sweep left
+  // them) and widen to FP64 exactly where they are used.
   extern __shared__ double sm[];
   const int p = a.p, q = a.q, q2 = q * q, pp = p * p;
   const int lg = __ffs(RR) - 1;
@@ -60,7 +64,7 @@ __device__ __forceinline__ void residual_body(const ResidualArgs& a, const int b
   double* My = Mx + q2 * p;
   const int ns = a.nsrc;
   double* st = My + q2 * p;                           // sources: [nsrc][q*q][RR]
-  double2* U = reinterpret_cast<double2*>(st + ns * RR * q2);   // grid values [p*p][RR]
+  float2* U = reinterpret_cast<float2*>(st + ns * RR * q2);     // grid values [p*p][RR]
   int* kij = reinterpret_cast<int*>(U + RR * pp);     // interior k -> i | jj << 8
   int* dmt = kij + q2;                                // edge slot k -> side | t << 2 | (wall+1) << 8
   for (int t = threadIdx.x; t < pp; t += blockDim.x) {
@@ -99,7 +103,7 @@ __device__ __forceinline__ void residual_body(const ResidualArgs& a, const int b
   int off[kPer];
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
-    const int idx = threadIdx.x + u * kBlock;
+    const int idx = threadIdx.x + u * kResBlock;
     off[u] = -1;
     if (idx < RR * pp) {
       const int node = idx >> lg, jr = idx & (RR - 1);
@@ -144,9 +148,9 @@ __device__ __forceinline__ void residual_body(const ResidualArgs& a, const int b
     if constexpr (SW) sc3 = a.swc[pole];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-      const int idx = threadIdx.x + u * kBlock;
+      const int idx = threadIdx.x + u * kResBlock;
       if (idx < RR * pp) {
-        U[idx] = make_double2(nxt[u].x, nxt[u].y);
+        U[idx] = nxt[u];
         if constexpr (SW) {
           const double yr = nxt[u].x, yi = nxt[u].y;
           e0[u] += sc3.c0.x * yr - sc3.c0.y * yi;
@@ -161,22 +165,23 @@ __device__ __forceinline__ void residual_body(const ResidualArgs& a, const int b
     const double2 al = pc.alpha;
     const double sre = pc.sig.x, sim = pc.sig.y;
     float2* gres = a.gres + ((long long)pole * a.w_pole + (long long)leaf * q2) * r + r0;
-    for (int idx = threadIdx.x; idx < RR * q2; idx += kBlock) {
+    for (int idx = threadIdx.x; idx < RR * q2; idx += kResBlock) {
       const int jr = idx & (RR - 1), k = idx >> lg;
       if (r0 + jr >= r) continue;
       const int ij = kij[k];
       const int i = ij & 255, jj = ij >> 8;
       const double* mx = Mx + ((jj - 1) * q + (i - 1)) * p;
       const double* my = My + ((i - 1) * q + (jj - 1)) * p;
-      const double2* ux = U + (p * jj) * RR + jr;     // row jj, stride RR
-      const double2* uy = U + i * RR + jr;            // column i, stride p RR
+      const float2* ux = U + (p * jj) * RR + jr;      // row jj, stride RR
+      const float2* uy = U + i * RR + jr;             // column i, stride p RR
       double2 ky = make_double2(0.0, 0.0);
       for (int l = 0; l < p; ++l) {
-        const double2 a1 = ux[l * RR], a2 = uy[l * p * RR];
-        ky.x += mx[l] * a1.x + my[l] * a2.x;
-        ky.y += mx[l] * a1.y + my[l] * a2.y;
+        const float2 a1 = ux[l * RR], a2 = uy[l * p * RR];
+        ky.x += mx[l] * double(a1.x) + my[l] * double(a2.x);
+        ky.y += mx[l] * double(a1.y) + my[l] * double(a2.y);
       }
-      const double2 y = U[(i + p * jj) * RR + jr];
+      const float2 yf = U[(i + p * jj) * RR + jr];
+      const double2 y = make_double2(yf.x, yf.y);
       // (K - sigma) y
       const double ar = ky.x - (sre * y.x - sim * y.y);
       const double ai = ky.y - (sre * y.y + sim * y.x);
@@ -189,7 +194,7 @@ __device__ __forceinline__ void residual_body(const ResidualArgs& a, const int b
     // outward normal derivative at the edge slots: sx D[0 or p-1][.] along the row,
     // sy D[0 or p-1][.] along the column
     double2* dn = a.dn + ((long long)pole * a.e_pole + L.vec_off) * r + r0;
-    for (int idx = threadIdx.x; idx < RR * L.e; idx += kBlock) {
+    for (int idx = threadIdx.x; idx < RR * L.e; idx += kResBlock) {
       const int jr = idx & (RR - 1), k = idx >> lg;
       if (r0 + jr >= r) continue;
       const int dmk = dmt[k];
@@ -197,13 +202,13 @@ __device__ __forceinline__ void residual_body(const ResidualArgs& a, const int b
       const bool xn = sd < 2, lo = (sd == 0 || sd == 2);
       const double* Dr = Ds + (lo ? 0 : (p - 1)) * p;
       const double sc = xn ? (lo ? -a.sx : a.sx) : (lo ? -a.sy : a.sy);
-      const double2* ul = xn ? U + (p * (t + 1)) * RR + jr : U + (t + 1) * RR + jr;
+      const float2* ul = xn ? U + (p * (t + 1)) * RR + jr : U + (t + 1) * RR + jr;
       const int ls = xn ? RR : p * RR;
       double2 v = make_double2(0.0, 0.0);
       for (int l = 0; l < p; ++l) {
-        const double2 uu = ul[l * ls];
-        v.x += Dr[l] * uu.x;
-        v.y += Dr[l] * uu.y;
+        const float2 uu = ul[l * ls];
+        v.x += Dr[l] * double(uu.x);
+        v.y += Dr[l] * double(uu.y);
       }
       double2 out = make_double2(sc * v.x, sc * v.y);
       if constexpr (SW) {
@@ -212,16 +217,16 @@ __device__ __forceinline__ void residual_body(const ResidualArgs& a, const int b
           // t = (-n2, n1): left -d_y, right +d_y, bottom +d_x, top -d_x
           const double tsc = (sd == 0) ? -a.sy : (sd == 1) ? a.sy : (sd == 2) ? a.sx : -a.sx;
           // the side's q non-corner nodes: (0|p-1, l+1) or (l+1, 0|p-1)
-          const double2* ut = (sd == 0) ? U + p * RR + jr
-                            : (sd == 1) ? U + (2 * p - 1) * RR + jr
-                            : (sd == 2) ? U + RR + jr : U + (p * (p - 1) + 1) * RR + jr;
+          const float2* ut = (sd == 0) ? U + p * RR + jr
+                           : (sd == 1) ? U + (2 * p - 1) * RR + jr
+                           : (sd == 2) ? U + RR + jr : U + (p * (p - 1) + 1) * RR + jr;
           const int ts = xn ? p * RR : RR;
           double2 dt = make_double2(0.0, 0.0);
           for (int l = 0; l < q; ++l) {
-            const double2 uu = ut[l * ts];
+            const float2 uu = ut[l * ts];
             const double d = a.Dq[t * q + l];
-            dt.x += d * uu.x;
-            dt.y += d * uu.y;
+            dt.x += d * double(uu.x);
+            dt.y += d * double(uu.y);
           }
           dt.x *= tsc;
           dt.y *= tsc;
@@ -240,7 +245,7 @@ __device__ __forceinline__ void residual_body(const ResidualArgs& a, const int b
     double* E = a.esum + (long long)leaf * 3 * pp * r + r0;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-      const int idx = threadIdx.x + u * kBlock;
+      const int idx = threadIdx.x + u * kResBlock;
       if (idx < RR * pp) {
         const int node = idx >> lg, jr = idx & (RR - 1);
         if (r0 + jr < r) {
@@ -254,12 +259,12 @@ __device__ __forceinline__ void residual_body(const ResidualArgs& a, const int b
 }
 
 template <bool SW>
-__global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a) {
+__global__ __launch_bounds__(kResBlock) void k_residual(ResidualArgs a) {
   residual_body<SW>(a, blockIdx.x);
 }
 
 template <bool SW>
-__global__ __launch_bounds__(kBlock) void k_residual_multi(Multi<ResidualArgs> m) {
+__global__ __launch_bounds__(kResBlock) void k_residual_multi(Multi<ResidualArgs> m) {
   int i;
   const int bid = m.locate(blockIdx.x, i);
   const ResidualArgs a = m.args[i];
@@ -270,16 +275,16 @@ __global__ __launch_bounds__(kBlock) void k_residual_multi(Multi<ResidualArgs> m
 size_t residual_lds_bytes(int p, int RR, int nsrc) {
   const int pp = p * p, q2 = (p - 2) * (p - 2);
   return sizeof(double) * (2 * (size_t)pp + 2 * (size_t)q2 * p + (size_t)nsrc * RR * q2) +
-         sizeof(double2) * (size_t)RR * pp + sizeof(int) * ((size_t)q2 + 4 * (p - 2));
+         sizeof(float2) * (size_t)RR * pp + sizeof(int) * ((size_t)q2 + 4 * (p - 2));
 }
 
 // Right-hand sides per block: up to 32, within 56 KiB of LDS (two to three
 // blocks per CU), at least 1 (then up to 160 KiB); the grid values of one
-// pole are at most 8 per thread.
+// pole are at most kPer per thread.
 int residual_rr(const ResidualArgs& a) {
   int RR = 32;
   while (RR > 1 && (RR / 2 >= a.nrhs || residual_lds_bytes(a.p, RR, a.nsrc) > 56 * 1024 ||
-                    RR * a.p * a.p > 8 * kBlock))
+                    RR * a.p * a.p > kPer * kResBlock))
     RR /= 2;
   return RR;
 }
@@ -296,8 +301,8 @@ hipError_t launch_residual_one(const ResidualArgs& a, int blocks, bool sw, size_
   if (blocks <= 0) return hipSuccess;
   const hipError_t e = sw ? allow_residual_lds<true>(lds, false) : allow_residual_lds<false>(lds, false);
   if (e != hipSuccess) return e;
-  if (sw) hipLaunchKernelGGL(k_residual<true>, dim3(blocks), dim3(kBlock), lds, s, a);
-  else hipLaunchKernelGGL(k_residual<false>, dim3(blocks), dim3(kBlock), lds, s, a);
+  if (sw) hipLaunchKernelGGL(k_residual<true>, dim3(blocks), dim3(kResBlock), lds, s, a);
+  else hipLaunchKernelGGL(k_residual<false>, dim3(blocks), dim3(kResBlock), lds, s, a);
   return hipGetLastError();
 }
 
@@ -306,8 +311,8 @@ hipError_t launch_residual_multi(const Multi<ResidualArgs>& m, int blocks, bool 
   if (blocks <= 0) return hipSuccess;
   const hipError_t e = sw ? allow_residual_lds<true>(lds, true) : allow_residual_lds<false>(lds, true);
   if (e != hipSuccess) return e;
-  if (sw) hipLaunchKernelGGL(k_residual_multi<true>, dim3(blocks), dim3(kBlock), lds, s, m);
-  else hipLaunchKernelGGL(k_residual_multi<false>, dim3(blocks), dim3(kBlock), lds, s, m);
+  if (sw) hipLaunchKernelGGL(k_residual_multi<true>, dim3(blocks), dim3(kResBlock), lds, s, m);
+  else hipLaunchKernelGGL(k_residual_multi<false>, dim3(blocks), dim3(kResBlock), lds, s, m);
   return hipGetLastError();
 }
 
