@@ -101,10 +101,15 @@ typedef enum {
                                         instance's stages in each candidate
                                         shape (one or two right-hand-side
                                         tiles per block; merges also one-wave
-                                        blocks and pole groups; the upward
+                                        blocks, pole groups and fused level
+                                        pairs; the upward
                                         element sweep also source staging)
                                         and keeps the fastest (hx_plan_tiles,
                                         hx_plan_variants)                    */
+#define HX_FLAG_FUSED_MERGES   0x20u /* run the lowest merge levels in fused
+                                        pairs, the level between them kept in
+                                        LDS (the autotuner, when also set,
+                                        may still choose otherwise)          */
 
 /* Mesh: [x0,x1] x [y0,y1] split into nex x ney equal elements, each with a
  * p x p Chebyshev-Lobatto grid (section 2.2).  nex and ney are powers of
@@ -250,7 +255,9 @@ hx_status hx_plan_tiles(const hx_plan* plan, int instance, int* tiles, int n);
  *     where the level's rows fit one 16-row tile, else four waves, 64
  *     rows); HX_STAGE_MERGE_UP also bit 1, set when every block serves
  *     one pole, clear when the blocks of levels with many boxes walk a
- *     group of poles;
+ *     group of poles; bit 2 set when the lowest levels run in fused pairs
+ *     (the level between them kept in LDS), clear when every level runs
+ *     its own launch;
  *   other stages: 0.
  * All 0 for an instance that runs one pass per right-hand side.  Every
  * variant gives bit-identical results.  HX_EINVAL for a bad instance id. */

@@ -584,6 +584,383 @@ __global__ __launch_bounds__(64 * WV) void k_merge_down_mm_multi(Multi<MmMergeAr
   merge_down_body<T, NT, WV>(a, bid);
 }
 
+// ---- two merge levels per launch ----------------------------------------------
+// A block takes one level-(l+1) box T, one pole and one RHS tile.  Upward,
+// the four level-(l-1) vectors under T are read once into LDS, the two
+// level-l merges write their h into LDS, and T's merge reads it from
+// there: only the g3 of both levels and T's h go to HBM.  Downward, T's u3
+// and exterior values go straight into the staged operands of its two
+// children, whose merges write the level-(l-1) vectors.  Every product,
+// staging and rounding is the one the per-level kernels perform, so the
+// results are bit-identical to two per-level launches.
+
+// Fields of one of two boxes, chosen by a wave-uniform index (no dynamic
+// indexing of a register array).
+struct BoxPair {
+  BoxDesc d0, d1;
+  __device__ const BoxDesc& operator[](int b) const { return b ? d1 : d0; }
+};
+
+template <class T, int NT>
+__device__ __forceinline__ void merge2_up_body(const MmMerge2Args<T>& a, const int bid) {
+  using C = typename MM<T>::C;
+  constexpr int RT = 16 * NT, BST = RT + 1;
+  extern __shared__ unsigned char smem[];
+  C* const lds = reinterpret_cast<C*>(smem);
+  const int n_rt = (a.nrhs + RT - 1) / RT;
+  int rest = bid;
+  const int rt = rest % n_rt; rest /= n_rt;
+  const int pole = rest % a.npole;
+  const int top = rest / a.npole;
+  const BoxDesc Tb = a.hi[top];
+  BoxPair P;
+  P.d0 = a.lo[Tb.a_box];
+  P.d1 = a.lo[Tb.b_box];
+  const int r = a.nrhs, c0 = rt * RT;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  // LDS: the four child vectors X [rows][RT], the two level-l outputs Y
+  // [rows][RT], the staged g3 operands S [rows][BST]
+  const int ce0 = P.d0.n1 + P.d0.n3, ce1 = P.d0.n2 + P.d0.n3;
+  const int ce2 = P.d1.n1 + P.d1.n3, ce3 = P.d1.n2 + P.d1.n3;
+  const int xo1 = ce0, xo2 = xo1 + ce1, xo3 = xo2 + ce2, nx = xo3 + ce3;
+  const int eA = P.d0.n1 + P.d0.n2, eB = P.d1.n1 + P.d1.n2;
+  C* const X = lds;
+  C* const Y = X + nx * RT;
+  C* const S = Y + (eA + eB) * RT;
+  const int pA = (P.d0.n3 + 3) & ~3;
+  const int tA = (eA + 15) >> 4, tB = (eB + 15) >> 4;
+  const int n1 = Tb.n1, n3 = Tb.n3, ext = Tb.n1 + Tb.n2;
+  const C* YT = a.ops + pole * a.pole_stride + Tb.op_off + (long long)n3 * (ext + n3);
+  // the operator loads of this wave's first tile of each level are issued
+  // first, so that they are in flight while the vectors are loaded
+  ARing<T> ring0, ringT;
+  if (wave < tA + tB) {
+    const int b = wave < tA ? 0 : 1;
+    const BoxDesc& D = P[b];
+    const int e = D.n1 + D.n2;
+    mm_prime(ring0, a.ops + pole * a.pole_stride + D.op_off + (long long)D.n3 * (e + D.n3), e,
+             (wave - (b ? tA : 0)) * 16, e, 0, D.n3);
+  }
+  if (wave * 16 < ext) mm_prime(ringT, YT, ext, wave * 16, ext, 0, n3);
+  const C* hc = a.child + (long long)pole * a.child_pole * r;
+  for (int idx = threadIdx.x; idx < nx * RT; idx += blockDim.x) {
+    const int k = idx / RT, j = idx - k * RT;
+    const int vec = k < xo1 ? P.d0.a_vec + k
+                  : k < xo2 ? P.d0.b_vec + (k - xo1)
+                  : k < xo3 ? P.d1.a_vec + (k - xo2) : P.d1.b_vec + (k - xo3);
+    C v;
+    v.x = v.y = T(0);
+    if (c0 + j < r) v = hc[(long long)vec * r + c0 + j];
+    X[idx] = v;
+  }
+  __syncthreads();
+  const double2* dp = a.dn ? a.dn + (long long)pole * a.dn_pole * r : nullptr;
+  // g3 of the two level-l boxes: h3a + h3b (+ the flux residual)
+  for (int b = 0; b < 2; ++b) {
+    const BoxDesc& D = P[b];
+    const int* i3a = a.idx + D.idx_off + D.n1 + D.n2;
+    const int* i3b = i3a + D.n3;
+    const int* ja = a.idx + D.j_off;
+    const C* xa = X + (b ? xo2 : 0) * RT;
+    const C* xb = X + (b ? xo3 : xo1) * RT;
+    C* Sb = S + (b ? pA * BST : 0);
+    C* g3 = a.g3_lo + ((long long)pole * a.g3_lo_pole + D.g3_off) * r;
+    const int pb = (D.n3 + 3) & ~3;
+    for (int idx = threadIdx.x; idx < pb * RT; idx += blockDim.x) {
+      const int k = idx / RT, j = idx - k * RT;
+      const int rhs = c0 + j;
+      C v;
+      v.x = v.y = T(0);
+      if (k < D.n3 && rhs < r) {
+        const C x = xa[i3a[k] * RT + j];
+        const C y = xb[i3b[k] * RT + j];
+        v.x = x.x + y.x;
+        v.y = x.y + y.y;
+        if (dp) {
+          const double2 da = dp[(long long)ja[k] * r + rhs];
+          const double2 db = dp[(long long)ja[D.n3 + k] * r + rhs];
+          v.x += T(da.x + db.x);
+          v.y += T(da.y + db.y);
+        }
+        g3[(long long)k * r + rhs] = v;
+      }
+      Sb[k * BST + j] = v;
+    }
+  }
+  __syncthreads();
+  // the level-l products, 16-row tiles of both boxes over the waves
+  {
+    for (int tile = wave; tile < tA + tB; tile += nw) {
+      const int b = tile < tA ? 0 : 1;
+      const BoxDesc& D = P[b];
+      const int ext = D.n1 + D.n2, row0 = (tile - (b ? tA : 0)) * 16;
+      const C* Yop = a.ops + pole * a.pole_stride + D.op_off + (long long)D.n3 * (ext + D.n3);
+      Acc<T, NT> acc;
+      acc.zero();
+      if (tile != wave) mm_prime(ring0, Yop, ext, row0, ext, 0, D.n3);
+      mm_run<T, NT>(acc, ring0, S + (b ? pA * BST : 0), BST);
+      const int* i1 = a.idx + D.idx_off;
+      const int* i2 = i1 + D.n1;
+      const C* xa = X + (b ? xo2 : 0) * RT;
+      const C* xb = X + (b ? xo3 : xo1) * RT;
+      C* yo = Y + (b ? eA : 0) * RT;
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = row0 + MM<T>::row(lane, v);
+          const int j = t * 16 + (lane & 15);
+          if (row < ext) {
+            const C base = row < D.n1 ? xa[i1[row] * RT + j] : xb[i2[row - D.n1] * RT + j];
+            C o;
+            o.x = T(double(base.x) - acc.vre(t, v));
+            o.y = T(double(base.y) - acc.vim(t, v));
+            yo[row * RT + j] = o;
+          }
+        }
+    }
+  }
+  __syncthreads();
+  // T: g3 from the level-l outputs, then its product into HBM
+  const int* i1 = a.idx + Tb.idx_off;
+  const int* i2 = i1 + n1;
+  const int* i3a = i2 + Tb.n2;
+  const int* i3b = i3a + n3;
+  {
+    const int* ja = a.idx + Tb.j_off;
+    C* g3 = a.g3_hi + ((long long)pole * a.g3_hi_pole + Tb.g3_off) * r;
+    const int pt = (n3 + 3) & ~3;
+    for (int idx = threadIdx.x; idx < pt * RT; idx += blockDim.x) {
+      const int k = idx / RT, j = idx - k * RT;
+      const int rhs = c0 + j;
+      C v;
+      v.x = v.y = T(0);
+      if (k < n3 && rhs < r) {
+        const C x = Y[i3a[k] * RT + j];
+        const C y = Y[(eA + i3b[k]) * RT + j];
+        v.x = x.x + y.x;
+        v.y = x.y + y.y;
+        if (dp) {
+          const double2 da = dp[(long long)ja[k] * r + rhs];
+          const double2 db = dp[(long long)ja[n3 + k] * r + rhs];
+          v.x += T(da.x + db.x);
+          v.y += T(da.y + db.y);
+        }
+        g3[(long long)k * r + rhs] = v;
+      }
+      S[k * BST + j] = v;
+    }
+  }
+  __syncthreads();
+  C* hp = a.self + ((long long)pole * a.self_pole + Tb.vec_off) * r;
+  for (int tile = wave; tile * 16 < ext; tile += nw) {
+    const int row0 = tile * 16;
+    Acc<T, NT> acc;
+    acc.zero();
+    if (tile != wave) mm_prime(ringT, YT, ext, row0, ext, 0, n3);
+    mm_run<T, NT>(acc, ringT, S, BST);
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = row0 + MM<T>::row(lane, v);
+        const int j = t * 16 + (lane & 15);
+        if (row < ext && c0 + j < r) {
+          const C base = row < n1 ? Y[i1[row] * RT + j] : Y[(eA + i2[row - n1]) * RT + j];
+          C o;
+          o.x = T(double(base.x) - acc.vre(t, v));
+          o.y = T(double(base.y) - acc.vim(t, v));
+          hp[(long long)row * r + c0 + j] = o;
+        }
+      }
+  }
+}
+
+template <class T, int NT>
+__device__ __forceinline__ void merge2_down_body(const MmMerge2Args<T>& a, const int bid) {
+  using C = typename MM<T>::C;
+  constexpr int RT = 16 * NT, BST = RT + 1;
+  extern __shared__ unsigned char smem[];
+  C* const lds = reinterpret_cast<C*>(smem);
+  const int n_rt = (a.nrhs + RT - 1) / RT;
+  int rest = bid;
+  const int rt = rest % n_rt; rest /= n_rt;
+  const int pole = rest % a.npole;
+  const int top = rest / a.npole;
+  const BoxDesc Tb = a.hi[top];
+  BoxPair P;
+  P.d0 = a.lo[Tb.a_box];
+  P.d1 = a.lo[Tb.b_box];
+  const int r = a.nrhs, c0 = rt * RT;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  // LDS: T's operand [u_ext; g3] and the children's [u_ext; g3], [rows][BST]
+  const int extT = Tb.n1 + Tb.n2, mT = extT + Tb.n3, mpT = (mT + 3) & ~3;
+  const int eA = P.d0.n1 + P.d0.n2, mA = eA + P.d0.n3, mpA = (mA + 3) & ~3;
+  const int eB = P.d1.n1 + P.d1.n2, mB = eB + P.d1.n3, mpB = (mB + 3) & ~3;
+  C* const PT = lds;
+  C* const SA = PT + mpT * BST;
+  C* const SB = SA + mpA * BST;
+  const int tA = (P.d0.n3 + 15) >> 4, tB = (P.d1.n3 + 15) >> 4;
+  const C* ZT = a.ops + pole * a.pole_stride + Tb.op_off;
+  // the operator loads of this wave's first tile of each level are issued
+  // first, so that they are in flight while the operands are loaded
+  ARing<T> ringT, ring0;
+  if (wave * 16 < Tb.n3) mm_prime(ringT, ZT, Tb.n3, wave * 16, Tb.n3, 0, mT);
+  if (wave < tA + tB) {
+    const int b = wave < tA ? 0 : 1;
+    const BoxDesc& D = P[b];
+    mm_prime(ring0, a.ops + pole * a.pole_stride + D.op_off, D.n3, (wave - (b ? tA : 0)) * 16, D.n3, 0,
+             b ? mB : mA);
+  }
+  {
+    const C* up = a.self + ((long long)pole * a.self_pole + Tb.vec_off) * r;
+    const C* g3 = a.g3_hi + ((long long)pole * a.g3_hi_pole + Tb.g3_off) * r;
+    for (int idx = threadIdx.x; idx < mpT * RT; idx += blockDim.x) {
+      const int k = idx / RT, j = idx - k * RT;
+      const int rhs = c0 + j;
+      C v;
+      v.x = v.y = T(0);
+      if (k < mT && rhs < r) v = k < extT ? up[(long long)k * r + rhs] : g3[(long long)(k - extT) * r + rhs];
+      PT[k * BST + j] = v;
+    }
+  }
+  for (int b = 0; b < 2; ++b) {
+    const BoxDesc& D = P[b];
+    const int e = b ? eB : eA, m = b ? mB : mA, mp = b ? mpB : mpA;
+    C* Sb = b ? SB : SA;
+    const C* g3 = a.g3_lo + ((long long)pole * a.g3_lo_pole + D.g3_off) * r;
+    for (int idx = threadIdx.x; idx < (mp - e) * RT; idx += blockDim.x) {
+      const int k = e + idx / RT, j = idx % RT;
+      const int rhs = c0 + j;
+      C v;
+      v.x = v.y = T(0);
+      if (k < m && rhs < r) v = g3[(long long)(k - e) * r + rhs];
+      Sb[k * BST + j] = v;
+    }
+  }
+  __syncthreads();
+  const int* i1 = a.idx + Tb.idx_off;
+  const int* i2 = i1 + Tb.n1;
+  const int* i3a = i2 + Tb.n2;
+  const int* i3b = i3a + Tb.n3;
+  // T's exterior values to the children's exterior rows
+  for (int idx = threadIdx.x; idx < extT * RT; idx += blockDim.x) {
+    const int k = idx / RT, j = idx - k * RT;
+    const C v = PT[k * BST + j];
+    if (k < Tb.n1) SA[i1[k] * BST + j] = v;
+    else SB[i2[k - Tb.n1] * BST + j] = v;
+  }
+  // T's u3 = -Z [u_ext; g3] to the children's interface rows
+  {
+    for (int tile = wave; tile * 16 < Tb.n3; tile += nw) {
+      const int row0 = tile * 16;
+      Acc<T, NT> acc;
+      acc.zero();
+      if (tile != wave) mm_prime(ringT, ZT, Tb.n3, row0, Tb.n3, 0, mT);
+      mm_run<T, NT>(acc, ringT, PT, BST);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = row0 + MM<T>::row(lane, v);
+          const int j = t * 16 + (lane & 15);
+          if (row < Tb.n3) {
+            C u3;
+            u3.x = T(-acc.vre(t, v));
+            u3.y = T(-acc.vim(t, v));
+            SA[i3a[row] * BST + j] = u3;
+            SB[i3b[row] * BST + j] = u3;
+          }
+        }
+    }
+  }
+  __syncthreads();
+  // the level-l boxes: exterior values and u3 into the level l-1 vectors
+  C* uc = a.child + (long long)pole * a.child_pole * r;
+  for (int b = 0; b < 2; ++b) {
+    const BoxDesc& D = P[b];
+    const int e = b ? eB : eA;
+    const C* Sb = b ? SB : SA;
+    const int* j1 = a.idx + D.idx_off;
+    const int* j2 = j1 + D.n1;
+    for (int idx = threadIdx.x; idx < e * RT; idx += blockDim.x) {
+      const int k = idx / RT, j = idx - k * RT;
+      const int rhs = c0 + j;
+      if (rhs >= r) continue;
+      const C v = Sb[k * BST + j];
+      if (k < D.n1) uc[(long long)(D.a_vec + j1[k]) * r + rhs] = v;
+      else uc[(long long)(D.b_vec + j2[k - D.n1]) * r + rhs] = v;
+    }
+  }
+  {
+    for (int tile = wave; tile < tA + tB; tile += nw) {
+      const int b = tile < tA ? 0 : 1;
+      const BoxDesc& D = P[b];
+      const int row0 = (tile - (b ? tA : 0)) * 16;
+      const int m = b ? mB : mA;
+      const C* Z = a.ops + pole * a.pole_stride + D.op_off;
+      Acc<T, NT> acc;
+      acc.zero();
+      if (tile != wave) mm_prime(ring0, Z, D.n3, row0, D.n3, 0, m);
+      mm_run<T, NT>(acc, ring0, b ? SB : SA, BST);
+      const int* j3a = a.idx + D.idx_off + D.n1 + D.n2;
+      const int* j3b = j3a + D.n3;
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = row0 + MM<T>::row(lane, v);
+          const int rhs = c0 + t * 16 + (lane & 15);
+          if (row < D.n3 && rhs < r) {
+            C u3;
+            u3.x = T(-acc.vre(t, v));
+            u3.y = T(-acc.vim(t, v));
+            uc[(long long)(D.a_vec + j3a[row]) * r + rhs] = u3;
+            uc[(long long)(D.b_vec + j3b[row]) * r + rhs] = u3;
+          }
+        }
+    }
+  }
+}
+
+template <class T, int NT>
+__global__ __launch_bounds__(kBlock) void k_merge2_up_mm(MmMerge2Args<T> a) {
+  merge2_up_body<T, NT>(a, xcd_block());
+}
+
+template <class T, int NT>
+__global__ __launch_bounds__(kBlock) void k_merge2_up_mm_multi(Multi<MmMerge2Args<T>> m) {
+  int i;
+  const int bid = m.locate(xcd_block(), i);
+  const MmMerge2Args<T> a = m.args[i];
+  merge2_up_body<T, NT>(a, bid);
+}
+
+template <class T, int NT>
+__global__ __launch_bounds__(kBlock) void k_merge2_down_mm(MmMerge2Args<T> a) {
+  merge2_down_body<T, NT>(a, xcd_block());
+}
+
+template <class T, int NT>
+__global__ __launch_bounds__(kBlock) void k_merge2_down_mm_multi(Multi<MmMerge2Args<T>> m) {
+  int i;
+  const int bid = m.locate(xcd_block(), i);
+  const MmMerge2Args<T> a = m.args[i];
+  merge2_down_body<T, NT>(a, bid);
+}
+
+template <class T>
+size_t merge2_up_lds_bytes(int nt, int child_rows, int mid_rows, int stage_rows) {
+  const int RT = 16 * nt;
+  return sizeof(typename MM<T>::C) *
+         ((size_t)RT * (child_rows + mid_rows) + (size_t)(RT + 1) * stage_rows);
+}
+
+template <class T>
+size_t merge2_down_lds_bytes(int nt, int rows) {
+  return sizeof(typename MM<T>::C) * (size_t)(16 * nt + 1) * rows;
+}
+
 // ---- leaf downward: y = w - S u_e (in place of w) -----------------------------
 template <class T, int NT>
 __device__ __forceinline__ void leaf_down_body(const MmLeafDownArgs<T>& a, const int bid) {
@@ -962,6 +1339,27 @@ HX_MERGE_LAUNCHERS(merge_up_mm)
 HX_MERGE_LAUNCHERS(merge_down_mm)
 #undef HX_MERGE_LAUNCHERS
 
+#define HX_MERGE2_LAUNCHERS(NAME)                                                                  \
+  template <class T>                                                                               \
+  hipError_t launch_##NAME##_multi(const Multi<MmMerge2Args<T>>& m, int blocks, int nt, size_t lds, \
+                                   hipStream_t s) {                                                \
+    if (blocks <= 0) return hipSuccess;                                                            \
+    if (nt == 2) hipLaunchKernelGGL((k_##NAME##_multi<T, 2>), dim3(blocks), dim3(kBlock), lds, s, m); \
+    else hipLaunchKernelGGL((k_##NAME##_multi<T, 1>), dim3(blocks), dim3(kBlock), lds, s, m);      \
+    return hipGetLastError();                                                                      \
+  }                                                                                                \
+  template <class T>                                                                               \
+  hipError_t launch_##NAME##_one(const MmMerge2Args<T>& a, int blocks, int nt, size_t lds,         \
+                                 hipStream_t s) {                                                  \
+    if (blocks <= 0) return hipSuccess;                                                            \
+    if (nt == 2) hipLaunchKernelGGL((k_##NAME<T, 2>), dim3(blocks), dim3(kBlock), lds, s, a);      \
+    else hipLaunchKernelGGL((k_##NAME<T, 1>), dim3(blocks), dim3(kBlock), lds, s, a);              \
+    return hipGetLastError();                                                                      \
+  }
+HX_MERGE2_LAUNCHERS(merge2_up_mm)
+HX_MERGE2_LAUNCHERS(merge2_down_mm)
+#undef HX_MERGE2_LAUNCHERS
+
 #define HX_INST(T)                                                                                     \
   template size_t leaf_up_lds_bytes<T>(int, int, bool, int);                                                      \
   template hipError_t launch_leaf_up_mm_multi<T>(const Multi<MmLeafUpArgs<T>>&, int, int, bool, size_t, hipStream_t); \
@@ -975,7 +1373,13 @@ HX_MERGE_LAUNCHERS(merge_down_mm)
   template hipError_t launch_merge_down_mm_one<T>(const MmMergeArgs<T>&, int, int, int, hipStream_t);          \
   template hipError_t launch_leaf_down_mm_one<T>(const MmLeafDownArgs<T>&, int, int, hipStream_t);        \
   template hipError_t launch_leaf_down_sum_mm_one<T>(const MmLeafDownArgs<T>&, int, int, hipStream_t);    \
-  template hipError_t launch_sw_root_mm_one<T>(const SwRootArgs<T>&, int, int, hipStream_t);
+  template hipError_t launch_sw_root_mm_one<T>(const SwRootArgs<T>&, int, int, hipStream_t);          \
+  template hipError_t launch_merge2_up_mm_multi<T>(const Multi<MmMerge2Args<T>>&, int, int, size_t, hipStream_t); \
+  template hipError_t launch_merge2_down_mm_multi<T>(const Multi<MmMerge2Args<T>>&, int, int, size_t, hipStream_t); \
+  template hipError_t launch_merge2_up_mm_one<T>(const MmMerge2Args<T>&, int, int, size_t, hipStream_t);   \
+  template hipError_t launch_merge2_down_mm_one<T>(const MmMerge2Args<T>&, int, int, size_t, hipStream_t); \
+  template size_t merge2_up_lds_bytes<T>(int, int, int, int);                                       \
+  template size_t merge2_down_lds_bytes<T>(int, int);
 HX_INST(float)
 HX_INST(double)
 #undef HX_INST

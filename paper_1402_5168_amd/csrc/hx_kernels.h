@@ -149,6 +149,30 @@ struct MmMergeArgs {
   int pole_group;
 };
 
+// Two merge levels in one launch, l and l + 1 (l >= 1): a block holds one
+// level-(l+1) box, one pole and one RHS tile; the level-l vectors between
+// the two merges stay in LDS.  Upward: child = level l-1 h, self = level
+// l+1 h; downward: child = level l-1 u, self = level l+1 u.
+template <class T>
+struct MmMerge2Args {
+  const typename Cplx<T>::type* ops;
+  long long pole_stride;
+  const BoxDesc* lo;   // level l boxes
+  const BoxDesc* hi;   // level l + 1 boxes
+  const int* idx;
+  int npole, nrhs;
+  typename Cplx<T>::type* child;
+  long long child_pole;
+  typename Cplx<T>::type* self;
+  long long self_pole;
+  typename Cplx<T>::type* g3_lo;
+  long long g3_lo_pole;
+  typename Cplx<T>::type* g3_hi;
+  long long g3_hi_pole;
+  const double2* dn;   // upward correction sweep, as in MmMergeArgs
+  long long dn_pole;
+};
+
 template <class T>
 struct MmLeafDownArgs {
   const typename Cplx<T>::type* ops;
@@ -284,6 +308,13 @@ hipError_t launch_residual_multi(const Multi<ResidualArgs>& m, int blocks, bool 
 // the table, all with the same tile count nt (1 or 2) and LDS bytes.
 template <class T> hipError_t launch_leaf_up_mm_multi(const Multi<MmLeafUpArgs<T>>& m, int blocks, int nt, bool xl, size_t lds, hipStream_t s);
 template <class T> hipError_t launch_merge_up_mm_multi(const Multi<MmMergeArgs<T>>& m, int blocks, int nt, int wv, hipStream_t s);
+template <class T> hipError_t launch_merge2_up_mm_multi(const Multi<MmMerge2Args<T>>& m, int blocks, int nt, size_t lds, hipStream_t s);
+template <class T> hipError_t launch_merge2_down_mm_multi(const Multi<MmMerge2Args<T>>& m, int blocks, int nt, size_t lds, hipStream_t s);
+template <class T> hipError_t launch_merge2_up_mm_one(const MmMerge2Args<T>& a, int blocks, int nt, size_t lds, hipStream_t s);
+template <class T> hipError_t launch_merge2_down_mm_one(const MmMerge2Args<T>& a, int blocks, int nt, size_t lds, hipStream_t s);
+// LDS bytes of a fused two-level block for the given box sizes.
+template <class T> size_t merge2_up_lds_bytes(int nt, int child_rows, int mid_rows, int stage_rows);
+template <class T> size_t merge2_down_lds_bytes(int nt, int rows);
 template <class T> hipError_t launch_merge_down_mm_multi(const Multi<MmMergeArgs<T>>& m, int blocks, int nt, int wv, hipStream_t s);
 template <class T> hipError_t launch_leaf_down_mm_multi(const Multi<MmLeafDownArgs<T>>& m, int blocks, int nt, hipStream_t s);
 template <class T> hipError_t launch_leaf_down_sum_mm_multi(const Multi<MmLeafDownArgs<T>>& m, int blocks, int nt, hipStream_t s);

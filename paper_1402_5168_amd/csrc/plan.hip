@@ -95,6 +95,10 @@ struct Level {
   size_t d_boxes = 0, d_h = 0, d_u = 0, d_g3 = 0;
 };
 
+// Stages of a step in launch order (the recorder's order key; the tuned
+// choices of an instance are kept per stage).
+enum StageOrder : int { O_PREP, O_LEAF_UP, O_MERGE_UP, O_ROOT, O_MERGE_DOWN, O_LEAF_DOWN, O_RESIDUAL, O_POST };
+
 struct Instance {
   hx_mesh mesh{};
   int q = 0, q2 = 0, n_leaf = 0, npole = 0, nrhs = 0, ncol = 0, M = 0;
@@ -113,6 +117,7 @@ struct Instance {
   int tune_wv[8] = {0, 0, 0, 0, 0, 0, 0, 0}; // merge stages: 1 = one-wave blocks at every level
   int tune_xl = 0;                          // upward elements: 2 = never stage the sources
   int tune_pg[8] = {0, 0, 0, 0, 0, 0, 0, 0}; // merge stages: 1 = one pole per block
+  int tune_fuse[8] = {0, 0, 0, 0, 0, 0, 0, 0}; // merge stages: 1 = fused pairs of low levels
   bool fp32 = false;                        // precision form: FP32 operators and sweeps
   // shallow water: wall nodes are exterior unknowns up to the root
   bool sw = false;
@@ -869,7 +874,7 @@ hx_status hx_plan_create(hx_plan** out, int precision, int device, unsigned flag
     return fail(HX_EINVAL, "unsupported precision %d", precision);
   if (device < 0) return fail(HX_EINVAL, "device %d", device);
   if (flags & ~(HX_FLAG_ALLOW_UNSTABLE | HX_FLAG_NO_GRAPH | HX_FLAG_CHECK_STATE | HX_FLAG_UNBATCHED |
-                HX_FLAG_AUTOTUNE))
+                HX_FLAG_AUTOTUNE | HX_FLAG_FUSED_MERGES))
     return fail(HX_EINVAL, "unknown flags 0x%x", flags);
   hx_plan* p = new hx_plan;
   p->device = device;
@@ -1112,6 +1117,8 @@ hx_status hx_plan_build(hx_plan* plan, void* workspace, size_t workspace_bytes, 
   HIP_OK(hipStreamSynchronize(B.s));
   drop_graph(plan);
   plan->tab_ready = false;
+  if (plan->flags & HX_FLAG_FUSED_MERGES)
+    for (Instance& I : plan->inst) I.tune_fuse[O_MERGE_UP] = I.tune_fuse[O_MERGE_DOWN] = 1;
   if (plan->flags & HX_FLAG_AUTOTUNE) HX_TRY(autotune(plan, B.ws, B.ws_bytes, B.s));
   plan->built = true;
   return HX_OK;
@@ -1168,9 +1175,9 @@ struct Prof {
 
 enum StageKind : int {
   K_LU_D, K_LU_F, K_MU_D, K_MU_F, K_MD_D, K_MD_F, K_LD_D, K_LD_F, K_LDS_D, K_LDS_F,
-  K_ROOT_D, K_ROOT_F, K_RES_W, K_RES_S, K_PREP, K_WALL, K_POST_D, K_POST_F
+  K_ROOT_D, K_ROOT_F, K_RES_W, K_RES_S, K_PREP, K_WALL, K_POST_D, K_POST_F,
+  K_MU2_D, K_MU2_F, K_MD2_D, K_MD2_F
 };
-enum StageOrder : int { O_PREP, O_LEAF_UP, O_MERGE_UP, O_ROOT, O_MERGE_DOWN, O_LEAF_DOWN, O_RESIDUAL, O_POST };
 
 
 struct Rec {
@@ -1228,6 +1235,40 @@ constexpr long long kMergeBlocks = 16384;
 int merge_pole_group(const Instance& I, int order, long long blocks) {
   if (I.tune_pg[order] == 1) return 1;
   return (int)std::max<long long>(1, std::min<long long>(I.npole, blocks / kMergeBlocks));
+}
+
+// When the tuner chose it, merge levels run in fused pairs (l, l + 1) from
+// the elements up while a fused block's LDS stays within kFuseLds (two
+// blocks or more per CU); by default every level has its own launch (the
+// fused blocks hold so much LDS that few fit on a CU, and on the workloads
+// measured the per-level launches were faster).  lds[l] > 0 marks the lower
+// level l of a pair and holds the LDS bytes of its launch.
+constexpr size_t kFuseLds = 64 * 1024;
+template <class T>
+std::vector<size_t> fused_pairs(const Instance& I, int order, int nt) {
+  const size_t nl = I.levels.size();
+  std::vector<size_t> lds(nl, 0);
+  if (I.tune_fuse[order] != 1) return lds;
+  auto r4 = [](int n) { return (n + 3) & ~3; };
+  for (size_t l = 1; l + 1 < nl; l += 2) {
+    size_t need = 0;
+    for (const BoxDesc& Tb : I.levels[l + 1].boxes) {
+      const BoxDesc& A = I.levels[l].boxes[Tb.a_box];
+      const BoxDesc& B = I.levels[l].boxes[Tb.b_box];
+      if (order == O_MERGE_UP) {
+        const int child = A.n1 + A.n2 + B.n1 + B.n2 + 2 * (A.n3 + B.n3);
+        const int mid = A.n1 + A.n2 + B.n1 + B.n2;
+        const int stage = std::max(r4(A.n3) + r4(B.n3), r4(Tb.n3));
+        need = std::max(need, hx::merge2_up_lds_bytes<T>(nt, child, mid, stage));
+      } else {
+        const int rows = r4(Tb.n1 + Tb.n2 + Tb.n3) + r4(A.n1 + A.n2 + A.n3) + r4(B.n1 + B.n2 + B.n3);
+        need = std::max(need, hx::merge2_down_lds_bytes<T>(nt, rows));
+      }
+    }
+    if (need > kFuseLds) break;   // the levels above are larger still
+    lds[l] = need;
+  }
+  return lds;
 }
 
 // Tile count and source staging of the first upward element sweep: two
@@ -1351,7 +1392,34 @@ void record_instance(const hx_plan* plan, const Instance& I, int inst, double* s
     R.add(pass, O_LEAF_UP, 0, dbl ? K_LU_D : K_LU_F, nt, et * npg, lds, lu, HX_K_LEAF_UP, inst,
           lu.x_lds);
 
+    const int mu_nt = stage_nt(I, O_MERGE_UP);
+    const std::vector<size_t> fu = fused_pairs<T>(I, O_MERGE_UP, mu_nt);
     for (size_t l = 1; l < nl; ++l) {
+      if (fu[l]) {   // levels l and l + 1 in one launch
+        hx::MmMerge2Args<T> m2{};
+        m2.ops = ops;
+        m2.pole_stride = I.pole_stride;
+        m2.lo = reinterpret_cast<const BoxDesc*>(a + I.levels[l].d_boxes);
+        m2.hi = reinterpret_cast<const BoxDesc*>(a + I.levels[l + 1].d_boxes);
+        m2.idx = idx;
+        m2.npole = I.npole;
+        m2.nrhs = I.nrhs;
+        m2.child = vec(I.levels[l - 1].d_h);
+        m2.child_pole = I.levels[l - 1].total_ext;
+        m2.self = vec(I.levels[l + 1].d_h);
+        m2.self_pole = I.levels[l + 1].total_ext;
+        m2.g3_lo = vec(I.levels[l].d_g3);
+        m2.g3_lo_pole = I.levels[l].total_n3;
+        m2.g3_hi = vec(I.levels[l + 1].d_g3);
+        m2.g3_hi_pole = I.levels[l + 1].total_n3;
+        m2.dn = pass ? dn : nullptr;
+        m2.dn_pole = I.levels[0].total_ext;
+        R.add(pass, O_MERGE_UP, (int)l, dbl ? K_MU2_D : K_MU2_F, mu_nt,
+              (long long)I.levels[l + 1].boxes.size() * I.npole * hx::mm_tiles(I.nrhs, mu_nt), fu[l],
+              m2, HX_K_MERGE_UP, inst, 0);
+        ++l;
+        continue;
+      }
       const Level& L = I.levels[l];
       hx::MmMergeArgs<T> m{};
       m.ops = ops;
@@ -1400,7 +1468,32 @@ void record_instance(const hx_plan* plan, const Instance& I, int inst, double* s
       R.add(pass, O_ROOT, 0, dbl ? K_ROOT_D : K_ROOT_F, rnt,
             (long long)I.npole * hx::mm_tiles(I.nrhs, rnt) * ra.row_groups, 0, ra, HX_K_SW_ROOT, inst);
     }
+    const int md_nt = stage_nt(I, O_MERGE_DOWN);
+    const std::vector<size_t> fd = fused_pairs<T>(I, O_MERGE_DOWN, md_nt);
     for (size_t l = nl - 1; l >= 1; --l) {
+      if (l >= 2 && fd[l - 1]) {   // levels l and l - 1 in one launch
+        hx::MmMerge2Args<T> m2{};
+        m2.ops = ops;
+        m2.pole_stride = I.pole_stride;
+        m2.lo = reinterpret_cast<const BoxDesc*>(a + I.levels[l - 1].d_boxes);
+        m2.hi = reinterpret_cast<const BoxDesc*>(a + I.levels[l].d_boxes);
+        m2.idx = idx;
+        m2.npole = I.npole;
+        m2.nrhs = I.nrhs;
+        m2.child = vec(I.levels[l - 2].d_u);
+        m2.child_pole = I.levels[l - 2].total_ext;
+        m2.self = vec(I.levels[l].d_u);
+        m2.self_pole = I.levels[l].total_ext;
+        m2.g3_lo = vec(I.levels[l - 1].d_g3);
+        m2.g3_lo_pole = I.levels[l - 1].total_n3;
+        m2.g3_hi = vec(I.levels[l].d_g3);
+        m2.g3_hi_pole = I.levels[l].total_n3;
+        R.add(pass, O_MERGE_DOWN, -(int)l, dbl ? K_MD2_D : K_MD2_F, md_nt,
+              (long long)I.levels[l].boxes.size() * I.npole * hx::mm_tiles(I.nrhs, md_nt), fd[l - 1],
+              m2, HX_K_MERGE_DOWN, inst, 0);
+        --l;
+        continue;
+      }
       const Level& L = I.levels[l];
       hx::MmMergeArgs<T> m{};
       m.ops = ops;
@@ -1620,6 +1713,10 @@ hipError_t launch_one(const unsigned char* blob, const Group& g, hipStream_t s) 
     case K_WALL: return hx::launch_sw_wall_one(host_args<hx::SwWallArgs>(blob, g), b, s);
     case K_POST_D: return hx::launch_sw_post_one<double>(host_args<hx::SwPostArgs<double>>(blob, g), b, g.lds, s);
     case K_POST_F: return hx::launch_sw_post_one<float>(host_args<hx::SwPostArgs<float>>(blob, g), b, g.lds, s);
+    case K_MU2_D: return hx::launch_merge2_up_mm_one<double>(host_args<hx::MmMerge2Args<double>>(blob, g), b, g.nt, g.lds, s);
+    case K_MU2_F: return hx::launch_merge2_up_mm_one<float>(host_args<hx::MmMerge2Args<float>>(blob, g), b, g.nt, g.lds, s);
+    case K_MD2_D: return hx::launch_merge2_down_mm_one<double>(host_args<hx::MmMerge2Args<double>>(blob, g), b, g.nt, g.lds, s);
+    case K_MD2_F: return hx::launch_merge2_down_mm_one<float>(host_args<hx::MmMerge2Args<float>>(blob, g), b, g.nt, g.lds, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1647,6 +1744,10 @@ hipError_t launch_group(const hx_plan* plan, const Group& g, const unsigned char
     case K_WALL: return hx::launch_sw_wall_multi(multi_of<hx::SwWallArgs>(plan, g), b, s);
     case K_POST_D: return hx::launch_sw_post_multi<double>(multi_of<hx::SwPostArgs<double>>(plan, g), b, g.lds, s);
     case K_POST_F: return hx::launch_sw_post_multi<float>(multi_of<hx::SwPostArgs<float>>(plan, g), b, g.lds, s);
+    case K_MU2_D: return hx::launch_merge2_up_mm_multi<double>(multi_of<hx::MmMerge2Args<double>>(plan, g), b, g.nt, g.lds, s);
+    case K_MU2_F: return hx::launch_merge2_up_mm_multi<float>(multi_of<hx::MmMerge2Args<float>>(plan, g), b, g.nt, g.lds, s);
+    case K_MD2_D: return hx::launch_merge2_down_mm_multi<double>(multi_of<hx::MmMerge2Args<double>>(plan, g), b, g.nt, g.lds, s);
+    case K_MD2_F: return hx::launch_merge2_down_mm_multi<float>(multi_of<hx::MmMerge2Args<float>>(plan, g), b, g.nt, g.lds, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1695,12 +1796,13 @@ hx_status tune_instance(hx_plan* plan, Instance& I, int k, double* scratch, hipS
     const bool merge = order == O_MERGE_UP || order == O_MERGE_DOWN;
     const bool up = order == O_LEAF_UP;
     // (tiles, shape mode): merges bit 0 = one-wave blocks (else the level
-    // rule), upward merges bit 1 = one pole per block (else pole groups);
+    // rule), upward merges bit 1 = one pole per block (else pole groups),
+    // merges bit 2 = fused pairs of low levels (else one launch per level);
     // upward elements 0 = stage the sources when they fit / 2 = never
     std::vector<std::pair<int, int>> cand;
     for (int nt = 1; nt <= (I.nrhs > 16 ? 2 : 1); ++nt)
-      for (int v : (order == O_MERGE_UP     ? std::vector<int>{0, 1, 2, 3}
-                    : order == O_MERGE_DOWN ? std::vector<int>{0, 1}
+      for (int v : (order == O_MERGE_UP     ? std::vector<int>{0, 1, 2, 3, 4, 5, 6, 7}
+                    : order == O_MERGE_DOWN ? std::vector<int>{0, 1, 4, 5}
                     : up                    ? std::vector<int>{0, 2}
                                             : std::vector<int>{0}))
         cand.push_back({nt, v});
@@ -1712,6 +1814,7 @@ hx_status tune_instance(hx_plan* plan, Instance& I, int k, double* scratch, hipS
       if (merge) {
         I.tune_wv[order] = c.second & 1;
         I.tune_pg[order] = (c.second >> 1) & 1;
+        I.tune_fuse[order] = (c.second >> 2) & 1;
       }
       if (up) I.tune_xl = c.second;
       Recorder R;
@@ -1745,6 +1848,7 @@ hx_status tune_instance(hx_plan* plan, Instance& I, int k, double* scratch, hipS
     if (merge) {
       I.tune_wv[order] = best_c.second & 1;
       I.tune_pg[order] = (best_c.second >> 1) & 1;
+      I.tune_fuse[order] = (best_c.second >> 2) & 1;
     }
     if (up) I.tune_xl = best_c.second;
   }
@@ -1997,7 +2101,8 @@ hx_status hx_plan_variants(const hx_plan* plan, int instance, int* variants, int
     if (b && st == HX_STAGE_LEAF_UP)
       v = (f32 ? leaf_up_shape<float>(I) : leaf_up_shape<double>(I)).staged ? 1 : 0;
     else if (b && (st == HX_STAGE_MERGE_UP || st == HX_STAGE_MERGE_DOWN))
-      v = (I.tune_wv[order] == 1 ? 1 : 0) | (I.tune_pg[order] == 1 ? 2 : 0);
+      v = (I.tune_wv[order] == 1 ? 1 : 0) | (I.tune_pg[order] == 1 ? 2 : 0) |
+          (I.tune_fuse[order] == 1 ? 4 : 0);
     variants[st] = v;
   }
   return HX_OK;

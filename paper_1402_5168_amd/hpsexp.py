@@ -24,6 +24,7 @@ HX_WAVE_DIRICHLET, HX_SW_SLIP = 0, 1
 HX_FP64, HX_FP32_REFINE = 0, 1
 HX_FLAG_ALLOW_UNSTABLE, HX_FLAG_NO_GRAPH, HX_FLAG_CHECK_STATE, HX_FLAG_UNBATCHED = 0x1, 0x2, 0x4, 0x8
 HX_FLAG_AUTOTUNE = 0x10
+HX_FLAG_FUSED_MERGES = 0x20
 
 
 class hx_mesh(ctypes.Structure):

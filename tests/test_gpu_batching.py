@@ -90,6 +90,20 @@ def test_fused_graph_equals_eager():
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fused_merge_pairs_equal_per_level_merges(precision):
+    """Fused pairs of low merge levels (the level between them kept in LDS)
+    perform the same products, stagings and roundings as one launch per
+    level: the results are bit-identical."""
+    say(f"6 instances, precision {precision}, fused merge pairs vs one launch per level")
+    from paper_1402_5168_amd import hpsexp
+    ws = batch()
+    fused = run(ws, 3, precision, flags=hpsexp.HX_FLAG_FUSED_MERGES)
+    ref = run(ws, 3, precision)
+    for a, b in zip(fused, ref):
+        assert np.array_equal(a, b)
+
+
 def test_autotuned_plan_equals_default_plan():
     """The autotuner only changes how many 16-column tiles a block takes;
     every column's arithmetic and order stay the same, so the results are
