@@ -103,46 +103,78 @@ __device__ __forceinline__ void mma_step(Acc<T, NT>& acc, const typename MM<T>::
 
 // The A loads of one product chunk.  mm_prime issues the first PF k-steps'
 // loads; a caller may prime before it stages B, so that their latency
-// overlaps the staging, then mm_run consumes them.  Every lane issues every
-// load: a row past nrows reads the last row (its results are never
-// stored), a column past kc reads the last column (it meets a zero row of
-// B), and the loads past the chunk's end are never consumed.  With no
-// branch around them the compiler counts the loads in flight exactly, so
-// each k-step waits only for its own load, PF loads behind the newest.
-template <class T>
+// overlaps the staging, then mm_run consumes them.  The loads go through a
+// buffer resource whose base (wave-uniform, in scalar registers) moves one
+// k-step at a time and whose size ends at the chunk's last column: a column
+// past kc, or a row past nrows (its offset is pushed out of range), reads
+// as zero, with no branch and no per-load address arithmetic in the vector
+// unit.  The compiler then counts the loads in flight exactly, so each
+// k-step waits only for its own load, PF loads behind the newest.
+template <class T, int PFN = 8>
 struct ARing {
-  static constexpr int PF = 8;
+  static constexpr int PF = PFN;
   typename MM<T>::C v[PF];
-  const typename MM<T>::C* ap;     // next load
-  const typename MM<T>::C* last;   // the lane's row, column kc - 1
-  long long step;
-  int kn;                          // column of the next load
+  const char* base;   // row row0 of the next load's first column (wave-uniform)
+  int step;           // bytes per k-step: 4 columns
+  int left;           // bytes of the chunk from base on (<= 0: none left)
+  unsigned voff;      // the lane's offset: row i of column kk, or out of range
   int kc;
 };
 
-template <class T>
-__device__ __forceinline__ void mm_prime(ARing<T>& g, const typename MM<T>::C* __restrict__ A,
-                                         long long lda, int row0, int nrows, int k_lo, int kc) {
-  const int lane = threadIdx.x & 63;
-  const int i = lane & 15, kk = lane >> 4;
-  const int row = min(row0 + i, nrows - 1);
-  g.ap = A + row + (long long)(k_lo + kk) * lda;
-  g.last = A + row + (long long)(k_lo + kc - 1) * lda;
-  g.step = 4 * lda;
-  g.kn = kk;
-  g.kc = kc;
-#pragma unroll
-  for (int u = 0; u < ARing<T>::PF; ++u) {
-    g.v[u] = ld_stream(g.kn < kc ? g.ap : g.last);
-    g.ap += g.step;
-    g.kn += 4;
-  }
+// Hardware word 3 of a raw buffer resource on this architecture family.
+constexpr int kBufWord3 = 0x00020000;
+
+__device__ __forceinline__ const char* uniform_ptr(const void* p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return reinterpret_cast<const char*>(((unsigned long long)hi << 32) | lo);
 }
 
-template <class T, int NT>
-__device__ __forceinline__ void mm_run(Acc<T, NT>& acc, ARing<T>& g,
+__device__ __forceinline__ void buf_load(float2& out, __amdgpu_buffer_rsrc_t r, unsigned voff) {
+  typedef float v2f __attribute__((ext_vector_type(2)));
+  const v2f v = __builtin_bit_cast(v2f, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0));
+  out = make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void buf_load(double2& out, __amdgpu_buffer_rsrc_t r, unsigned voff) {
+  typedef double v2d __attribute__((ext_vector_type(2)));
+  const v2d v = __builtin_bit_cast(v2d, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0));
+  out = make_double2(v.x, v.y);
+}
+
+template <class T, int PF>
+__device__ __forceinline__ void ring_load(ARing<T, PF>& g, int u) {
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(g.base), 0, max(g.left, 0), kBufWord3);
+  buf_load(g.v[u], r, g.voff);
+  g.base += g.step;
+  g.left -= g.step;
+}
+
+template <class T, int PF>
+__device__ __forceinline__ void mm_prime(ARing<T, PF>& g, const typename MM<T>::C* __restrict__ A,
+                                         long long lda, int row0, int nrows, int k_lo, int kc) {
+  using C = typename MM<T>::C;
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 15, kk = lane >> 4;
+  row0 = __builtin_amdgcn_readfirstlane(row0);
+  g.base = uniform_ptr(A + row0 + (long long)k_lo * lda);
+  g.step = (int)(4 * lda * (long long)sizeof(C));
+  g.left = (int)(((long long)kc * lda - row0) * (long long)sizeof(C));
+  g.voff = row0 + i < nrows ? (unsigned)((i + kk * lda) * (long long)sizeof(C)) : 0x80000000u;
+  g.kc = kc;
+#pragma unroll
+  for (int u = 0; u < PF; ++u) ring_load(g, u);
+}
+
+// The FP32 accumulators flush into the FP64 sums every kFlush k-steps,
+// whatever the depth of the ring, so that every ring gives the same sums.
+constexpr int kFlush = 8;
+
+template <class T, int NT, int PF>
+__device__ __forceinline__ void mm_run(Acc<T, NT>& acc, ARing<T, PF>& g,
                                        const typename MM<T>::C* __restrict__ Bs, int bst) {
-  constexpr int PF = ARing<T>::PF;
+  static_assert(PF % kFlush == 0, "ring depth must be a multiple of the flush interval");
   const int kk = (threadIdx.x & 63) >> 4;
   const int kc = g.kc;
   const int nsteps = (kc + 3) >> 2;
@@ -153,27 +185,26 @@ __device__ __forceinline__ void mm_run(Acc<T, NT>& acc, ARing<T>& g,
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
       const typename MM<T>::C a = g.v[u];
-      g.v[u] = ld_stream(g.kn < kc ? g.ap : g.last);
-      g.ap += g.step;
-      g.kn += 4;
+      ring_load(g, u);
       mma_step<T, NT>(acc, a, Bk);
       Bk += bstep;
+      if (u % kFlush == kFlush - 1) acc.flush();
     }
-    acc.flush();
   }
 #pragma unroll
   for (int u = 0; u < PF; ++u)
     if (s0 + u < nsteps) {
       mma_step<T, NT>(acc, g.v[u], Bk);
       Bk += bstep;
+      if (u % kFlush == kFlush - 1) acc.flush();
     }
   acc.flush();
 }
 
 // One wave: acc += A[its 16-row tile, columns k_lo .. k_lo+kc) * Bs[0..kc).
-// A points at row 0 of the operator; rows >= nrows and columns >= kc give 0
-// (no load is issued for them).  Bs holds kc rows rounded up to a multiple
-// of 4, zero-padded, with row stride bst.
+// A points at row 0 of the operator (column-major, leading dimension lda >=
+// nrows); rows >= nrows and columns >= kc read as 0.  Bs holds kc rows
+// rounded up to a multiple of 4, zero-padded, with row stride bst.
 //
 // A complex tile product is four real MFMAs into two accumulators:
 //   re += a.re b.re,  im += a.re b.im,  re += (-a.im) b.im,  im += a.im b.re,
@@ -181,11 +212,11 @@ __device__ __forceinline__ void mm_run(Acc<T, NT>& acc, ARing<T>& g,
 // Each k-step of 4 columns needs one complex A entry per lane from HBM; a
 // ring of PF registers keeps the next PF k-steps' loads in flight while
 // the current MFMAs run, so a wave does not stall on HBM latency.
-template <class T, int NT>
+template <class T, int NT, int PF = 8>
 __device__ __forceinline__ void mm_chunk(Acc<T, NT>& acc, const typename MM<T>::C* __restrict__ A,
                                          long long lda, int row0, int nrows, int k_lo, int kc,
                                          const typename MM<T>::C* __restrict__ Bs, int bst) {
-  ARing<T> g;
+  ARing<T, PF> g;
   mm_prime(g, A, lda, row0, nrows, k_lo, kc);
   mm_run<T, NT>(acc, g, Bs, bst);
 }
