@@ -1782,7 +1782,7 @@ constexpr int kTunedOrders[HX_STAGES] = {O_LEAF_UP, O_MERGE_UP, O_ROOT, O_MERGE_
 
 // Autotuner: for every batched instance and every tuned stage, launch that
 // stage of the first sweep (all its levels) in each candidate shape on a
-// scratch state in the build workspace, time the best of three runs of
+// scratch state in the build workspace, time the best of five runs of
 // each, keep the fastest.  Candidates: 1 or 2 right-hand-side tiles per
 // block (more than 16 right-hand sides only); for the merge stages also
 // one-wave blocks at every level against the level rule of merge_wv, and
@@ -1830,7 +1830,7 @@ hx_status tune_instance(hx_plan* plan, Instance& I, int k, double* scratch, hipS
       HIP_OK(hipMemcpyAsync(plan->arena + plan->d_tab, blob.data(), blob.size(), hipMemcpyHostToDevice, s));
       HIP_OK(hipStreamSynchronize(s));
       float t_min = 1e30f;
-      for (int rep = 0; rep < 4; ++rep) {   // the first run warms up
+      for (int rep = 0; rep < 6; ++rep) {   // the first run warms up
         HIP_OK(hipEventRecord(e0, s));
         for (const Group& g : groups) HIP_OK(launch_group(plan, g, blob.data(), s));
         HIP_OK(hipEventRecord(e1, s));
