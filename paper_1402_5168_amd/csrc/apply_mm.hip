@@ -167,14 +167,15 @@ __device__ __forceinline__ void mm_prime(ARing<T, PF>& g, const typename MM<T>::
   for (int u = 0; u < PF; ++u) ring_load(g, u);
 }
 
-// The FP32 accumulators flush into the FP64 sums every kFlush k-steps,
-// whatever the depth of the ring, so that every ring gives the same sums.
+// The FP32 accumulators flush into the FP64 sums every FL k-steps (kFlush
+// unless the caller chooses another), whatever the depth of the ring, so
+// that every ring gives the same sums.
 constexpr int kFlush = 8;
 
-template <class T, int NT, int PF>
+template <class T, int NT, int PF, int FL = kFlush>
 __device__ __forceinline__ void mm_run(Acc<T, NT>& acc, ARing<T, PF>& g,
                                        const typename MM<T>::C* __restrict__ Bs, int bst) {
-  static_assert(PF % kFlush == 0, "ring depth must be a multiple of the flush interval");
+  static_assert(PF % FL == 0 || FL % PF == 0, "ring depth and flush interval");
   const int kk = (threadIdx.x & 63) >> 4;
   const int kc = g.kc;
   const int nsteps = (kc + 3) >> 2;
@@ -182,21 +183,23 @@ __device__ __forceinline__ void mm_run(Acc<T, NT>& acc, ARing<T, PF>& g,
   const int bstep = 4 * bst;
   int s0 = 0;
   for (; s0 + PF <= nsteps; s0 += PF) {
+    if (FL > PF && s0 > 0 && s0 % FL == 0) acc.flush();
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
       const typename MM<T>::C a = g.v[u];
       ring_load(g, u);
       mma_step<T, NT>(acc, a, Bk);
       Bk += bstep;
-      if (u % kFlush == kFlush - 1) acc.flush();
+      if (FL <= PF && u % FL == FL - 1) acc.flush();
     }
   }
+  if (FL > PF && s0 > 0 && s0 % FL == 0 && s0 < nsteps) acc.flush();
 #pragma unroll
   for (int u = 0; u < PF; ++u)
     if (s0 + u < nsteps) {
       mma_step<T, NT>(acc, g.v[u], Bk);
       Bk += bstep;
-      if (u % kFlush == kFlush - 1) acc.flush();
+      if (FL <= PF && u % FL == FL - 1) acc.flush();
     }
   acc.flush();
 }
@@ -212,13 +215,13 @@ __device__ __forceinline__ void mm_run(Acc<T, NT>& acc, ARing<T, PF>& g,
 // Each k-step of 4 columns needs one complex A entry per lane from HBM; a
 // ring of PF registers keeps the next PF k-steps' loads in flight while
 // the current MFMAs run, so a wave does not stall on HBM latency.
-template <class T, int NT, int PF = 8>
+template <class T, int NT, int PF = 8, int FL = kFlush>
 __device__ __forceinline__ void mm_chunk(Acc<T, NT>& acc, const typename MM<T>::C* __restrict__ A,
                                          long long lda, int row0, int nrows, int k_lo, int kc,
                                          const typename MM<T>::C* __restrict__ Bs, int bst) {
   ARing<T, PF> g;
   mm_prime(g, A, lda, row0, nrows, k_lo, kc);
-  mm_run<T, NT>(acc, g, Bs, bst);
+  mm_run<T, NT, PF, FL>(acc, g, Bs, bst);
 }
 
 // The dispatcher hands blocks to the eight XCDs in turn (block b to XCD
@@ -354,7 +357,8 @@ __device__ __forceinline__ void leaf_up_body(const MmLeafUpArgs<T>& a, const int
     for (int tile = wave; tile * 16 < q2; tile += kBlock / 64) {
       Acc<T, NT> acc;
       acc.zero();
-      mm_chunk<T, NT>(acc, W, q2, tile * 16, q2, 0, q2, gs, BST);
+      // (products of depth q^2 <= 256: FP64 flushes every 16 k-steps suffice)
+      mm_chunk<T, NT, 8, 16>(acc, W, q2, tile * 16, q2, 0, q2, gs, BST);
       mm_emit<T, NT>(acc, tile * 16, q2, [&](int row, int j, C c) {
         const int rhs = rt * RT + j;
         if (rhs < r) w[(long long)row * r + rhs] = c;
