@@ -1781,7 +1781,7 @@ hx_status prepare_tables(hx_plan* plan, double* const* states, hipStream_t s) {
 constexpr int kTunedOrders[HX_STAGES] = {O_LEAF_UP, O_MERGE_UP, O_ROOT, O_MERGE_DOWN, O_LEAF_DOWN};
 
 // Autotuner: for every batched instance and every tuned stage, launch that
-// stage of the first sweep (all its levels) in each candidate shape on a
+// stage of every sweep (all its levels) in each candidate shape on a
 // scratch state in the build workspace, time the best of five runs of
 // each, keep the fastest.  Candidates: 1 or 2 right-hand-side tiles per
 // block (more than 16 right-hand sides only); for the merge stages also
@@ -1824,8 +1824,11 @@ hx_status tune_instance(hx_plan* plan, Instance& I, int k, double* scratch, hipS
       Recorder R;
       record_instance<T>(plan, I, k, scratch, R);
       Recorder one;
+      // the stage in every sweep of the step (the precision form's
+      // correction sweep runs other kernels for some stages, e.g. the
+      // downward elements fused with the pole sum)
       for (const Rec& r : R.recs)
-        if (r.pass == 0 && r.order == order) one.recs.push_back(r);
+        if (r.order == order) one.recs.push_back(r);
       if (one.recs.empty()) break;
       std::vector<Group> groups;
       std::vector<unsigned char> blob;
