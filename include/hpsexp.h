@@ -11,9 +11,10 @@
  * 2.3): dense per-element solution operators, then an upward and a
  * downward sweep over a binary merge tree of interface operators.
  *
- * Problem handled: the wave equation in first-order form
+ * Problems handled: linearised rotating shallow water with slip walls
+ * (HX_SW_SLIP, below) and the wave equation in first-order form
  *     u_t = v,   v_t = div(c(x)^2 grad u)   on a rectangle,
- * with homogeneous Dirichlet data, for which
+ * with homogeneous Dirichlet data (HX_WAVE_DIRICHLET), for which
  *     (tau L - alpha)(u, v) = (u0, v0)  <=>  (K - s) u = (alpha u0 + tau v0) / tau^2,
  *     v = (alpha u + u0) / tau,  K = div(c^2 grad .),  s = (alpha / tau)^2.
  *
