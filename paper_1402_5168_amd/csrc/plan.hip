@@ -1149,8 +1149,8 @@ struct Prof {
     return HX_OK;
   }
   ~Prof() {
-    for (auto e : start) hipEventDestroy(e);
-    for (auto e : stop) hipEventDestroy(e);
+    for (auto e : start) (void)hipEventDestroy(e);   // teardown: nothing to report
+    for (auto e : stop) (void)hipEventDestroy(e);
   }
 };
 
@@ -1866,7 +1866,7 @@ hx_status autotune(hx_plan* plan, char* ws, size_t ws_bytes, hipStream_t s) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_OK(hipEventCreate(&e0));
   HIP_OK(hipEventCreate(&e1));
-  struct EvGuard { hipEvent_t a, b; ~EvGuard() { hipEventDestroy(a); hipEventDestroy(b); } } g{e0, e1};
+  struct EvGuard { hipEvent_t a, b; ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } g{e0, e1};
   hx_status st = HX_OK;
   for (size_t k = 0; k < plan->inst.size() && st == HX_OK; ++k) {
     Instance& I = plan->inst[k];
@@ -1996,8 +1996,8 @@ hx_status enqueue_step(hx_plan* plan, double* const* states, hipStream_t s, Prof
 }
 
 void drop_graph(hx_plan* plan) {
-  if (plan->graph_exec) hipGraphExecDestroy(plan->graph_exec);
-  if (plan->graph) hipGraphDestroy(plan->graph);
+  if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
   plan->graph_exec = nullptr;
   plan->graph = nullptr;
   plan->graph_states.clear();
@@ -2043,7 +2043,7 @@ hx_status hx_step(hx_plan* plan, double* const* states, int n_steps, void* strea
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(s, &g);
     if (st != HX_OK) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return st;
     }
     HIP_OK(ec);
