@@ -84,20 +84,27 @@ struct Acc {
   }
 };
 
-// One complex k-step of 4 columns on a 16-row tile: acc += a * Bk.
+// One complex k-step of 4 columns on a 16-row tile: acc += a * Bk.  The
+// first half-products of every column tile are issued before the second
+// halves, so that MFMAs into the same accumulator sit further apart.
 template <class T, int NT>
 __device__ __forceinline__ void mma_step(Acc<T, NT>& acc, const typename MM<T>::C a,
                                          const typename MM<T>::C* __restrict__ Bk) {
   using C = typename MM<T>::C;
   const int i = threadIdx.x & 15;
   const T nay = -a.y;
+  C b[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) b[t] = Bk[t * 16 + i];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const C b = Bk[t * 16 + i];
-    acc.re[t] = MM<T>::mma(a.x, b.x, acc.re[t]);
-    acc.im[t] = MM<T>::mma(a.x, b.y, acc.im[t]);
-    acc.re[t] = MM<T>::mma(nay, b.y, acc.re[t]);
-    acc.im[t] = MM<T>::mma(a.y, b.x, acc.im[t]);
+    acc.re[t] = MM<T>::mma(a.x, b[t].x, acc.re[t]);
+    acc.im[t] = MM<T>::mma(a.x, b[t].y, acc.im[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    acc.re[t] = MM<T>::mma(nay, b[t].y, acc.re[t]);
+    acc.im[t] = MM<T>::mma(a.y, b[t].x, acc.im[t]);
   }
 }
 
