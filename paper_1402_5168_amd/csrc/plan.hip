@@ -1808,7 +1808,7 @@ hx_status tune_instance(hx_plan* plan, Instance& I, int k, double* scratch, hipS
         cand.push_back({nt, v});
     if (cand.size() < 2) continue;
     // the default shape first; another shape replaces the best so far only
-    // when at least 3% faster, so that timing noise does not flip choices
+    // when at least 1% faster, so that timing noise does not flip choices
     const std::pair<int, int> dflt{I.nrhs > 16 ? 2 : 1, 0};
     std::stable_partition(cand.begin(), cand.end(), [&](const std::pair<int, int>& c) { return c == dflt; });
     float best = 1e30f;
@@ -1846,7 +1846,7 @@ hx_status tune_instance(hx_plan* plan, Instance& I, int k, double* scratch, hipS
         HIP_OK(hipEventElapsedTime(&ms, e0, e1));
         if (rep > 0) t_min = std::min(t_min, ms);
       }
-      if (t_min < best * 0.97f) {
+      if (t_min < best * 0.99f) {
         best = t_min;
         best_c = c;
       }
