@@ -2107,9 +2107,13 @@ hx_status hx_plan_variants(const hx_plan* plan, int instance, int* variants, int
     int v = 0;
     if (b && st == HX_STAGE_LEAF_UP)
       v = (f32 ? leaf_up_shape<float>(I) : leaf_up_shape<double>(I)).staged ? 1 : 0;
-    else if (b && (st == HX_STAGE_MERGE_UP || st == HX_STAGE_MERGE_DOWN))
-      v = (I.tune_wv[order] == 1 ? 1 : 0) | (I.tune_pg[order] == 1 ? 2 : 0) |
-          (I.tune_fuse[order] == 1 ? 4 : 0);
+    else if (b && (st == HX_STAGE_MERGE_UP || st == HX_STAGE_MERGE_DOWN)) {
+      // fused pairs count only where some pair fits the LDS bound
+      const int nt = stage_nt(I, order);
+      const std::vector<size_t> fp = f32 ? fused_pairs<float>(I, order, nt) : fused_pairs<double>(I, order, nt);
+      const bool fused = std::any_of(fp.begin(), fp.end(), [](size_t x) { return x > 0; });
+      v = (I.tune_wv[order] == 1 ? 1 : 0) | (I.tune_pg[order] == 1 ? 2 : 0) | (fused ? 4 : 0);
+    }
     variants[st] = v;
   }
   return HX_OK;
