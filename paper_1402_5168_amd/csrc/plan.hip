@@ -1231,7 +1231,7 @@ int merge_wv(const Instance& I, int order, int rows) {
 // per block for levels with fewer), unless the tuner chose one pole per
 // block.  A block then pays its descriptor and index loads once for the
 // whole group.
-constexpr long long kMergeBlocks = 16384;
+constexpr long long kMergeBlocks = 4096;
 int merge_pole_group(const Instance& I, int order, long long blocks) {
   if (I.tune_pg[order] == 1) return 1;
   return (int)std::max<long long>(1, std::min<long long>(I.npole, blocks / kMergeBlocks));
