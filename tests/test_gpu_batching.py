@@ -105,10 +105,11 @@ def test_fused_merge_pairs_equal_per_level_merges(precision):
 
 
 def test_autotuned_plan_equals_default_plan():
-    """The autotuner only changes how many 16-column tiles a block takes;
-    every column's arithmetic and order stay the same, so the results are
-    bit-identical to the default tile rule."""
-    say("6 instances, precision form, autotuned tiles vs default tiles")
+    """The autotuner only changes kernel shapes (16-column tiles per block,
+    source staging, waves per block, pole groups, fused merge pairs); every
+    column's arithmetic and order stay the same, so the results are
+    bit-identical to the default shapes."""
+    say("6 instances, precision form, autotuned shapes vs default shapes")
     torch = _torch()
     from paper_1402_5168_amd import hpsexp
     ws = batch()
