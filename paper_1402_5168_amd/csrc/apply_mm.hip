@@ -4,11 +4,10 @@
 // step, so each sweep becomes a batch of small complex GEMMs
 //     C (rows x RT) = A (rows x m, column-major, HBM) * B (m x RT, LDS),
 // RT = 16 or 32 right-hand sides per block.  A complex product is four real
-// MFMAs (v_mfma_*_16x16x4) into four accumulators (re*re, im*im, re*im,
-// im*re) combined at the end.  A wave owns one 16-row tile; it loads each
-// A entry exactly once (16 consecutive rows of 4 columns per instruction)
-// and reads its B fragment from LDS, where B is staged in k-chunks by the
-// whole block.  Vectors are stored [pole][node][rhs] (rhs fastest), so the
+// MFMAs (v_mfma_*_16x16x4) into two accumulators, the real and the
+// imaginary part.  A wave owns one 16-row tile; it streams each A entry
+// exactly once (16 consecutive rows of 4 columns per load) and reads its B
+// fragment from LDS, where B is staged in k-chunks by the whole block.  Vectors are stored [pole][node][rhs] (rhs fastest), so the
 // B gathers and the C stores of 16 consecutive right-hand sides are
 // contiguous.
 #include "hx_kernels.h"
@@ -411,7 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_up_mm_multi(Multi<MmLeafUpArgs<
 }
 
 // ---- merge upward: g3 = h3a + h3b (- j3), h_par = [h1a; h2b] - Y g3 ----------
-// block = (box, pole, rhs tile, row group of 64 rows of Y)
+// block = (box, group of poles, rhs tile, row group of 16 x WV rows of Y)
 template <class T, int NT, int WV>
 __device__ __forceinline__ void merge_up_body(const MmMergeArgs<T>& a, const int bid) {
   using C = typename MM<T>::C;
