@@ -561,17 +561,9 @@ __device__ __forceinline__ void merge_down_body(const MmMergeArgs<T>& a, const i
     ia[v] = row < n3 ? i3a[row] : 0;
     ib[v] = row < n3 ? i3b[row] : 0;
   }
-  if (rg == 0) {
-    for (int idx = threadIdx.x; idx < ext * RT; idx += blockDim.x) {
-      const int k = idx / RT, j = idx - k * RT;
-      const int rhs = rt * RT + j;
-      if (rhs >= r) continue;
-      const C v = up[(long long)k * r + rhs];
-      if (k < n1) uc[(long long)(B.a_vec + i1[k]) * r + rhs] = v;
-      else uc[(long long)(B.b_vec + i2[k - n1]) * r + rhs] = v;
-    }
-  }
-  // each chunk's operator loads are issued before its B is staged
+  // each chunk's operator loads are issued before its B is staged; row group
+  // 0 also copies the exterior values it stages to the children (one read
+  // of u_ext serves both: a separate copy pass re-read it from HBM)
   const C* Z = a.ops + pole * a.pole_stride + B.op_off;
   ARing<T> ring;
   if (row0 < n3) mm_prime(ring, Z, n3, row0, n3, 0, min(KC, m));
@@ -586,7 +578,13 @@ __device__ __forceinline__ void merge_down_body(const MmMergeArgs<T>& a, const i
       v.x = v.y = T(0);
       if (k < kc && rhs < r) {
         const int kg = k0 + k;
-        v = (kg < ext) ? up[(long long)kg * r + rhs] : g3[(long long)(kg - ext) * r + rhs];
+        if (kg < ext) {
+          v = up[(long long)kg * r + rhs];
+          if (rg == 0)
+            uc[(long long)(kg < n1 ? B.a_vec + i1[kg] : B.b_vec + i2[kg - n1]) * r + rhs] = v;
+        } else {
+          v = g3[(long long)(kg - ext) * r + rhs];
+        }
       }
       Bs[k * BST + j] = v;
     }
