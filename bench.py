@@ -15,9 +15,12 @@ operator already resident in HBM; the build stage is timed separately.
 Prints one JSON line.
 
 Roofline: the same K steps are run again through hx_step_profile, which
-brackets every kernel with HIP events on its launch stream; the dominant
-kernel's algorithmic flops (batched) or bytes (one right-hand side) per
-launch divided by its mean duration is compared with the MI355X peak.
+brackets every kernel with HIP events on its launch stream.  Batched wave
+runs put every kernel class (all its launches in a step) against its own
+roofline, from its algorithmic bytes and flops per step (`stages`), and
+report the class with the most time per step as the roofline object; with
+one right-hand side the element upward sweep's bytes per launch over its
+mean duration are compared with the HBM peak.
 cpu_baseline: the FP64 CPU oracle (sparse LU of the assembled collocation
 system) timed on a bounded sample of the same workload.
 """
@@ -39,35 +42,42 @@ FP32_PEAK_TFLOPS = 157.3      # MI355X dense FP32 (vector and matrix)
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_wave_64x64_p10_fp32refine_r32.md")
-TRAFFIC_SOURCES = ("apply_mm.hip", "hx_kernels.h", "hx_internal.h")
+TRAFFIC_SOURCES = ("apply_mm.hip", "residual.hip", "plan.hip", "hx_kernels.h", "hx_internal.h")
 
 
-def measured_traffic(kernels):
-    """HBM bytes per launch of the upward element sweep, averaged over the
-    given kernel instantiations (one per launch of a step: the first sweep
-    and the correction sweep), from the committed counter record of the
-    default workload; None when the record is missing, lacks one of them,
-    or the kernel sources changed since it was taken."""
+def sources_digest() -> str:
+    """SHA-256 over the kernel and launch-plan sources the record depends on."""
     import hashlib
-    import re
 
-    if not os.path.exists(TRAFFIC_RECORD):
-        return None
-    rec = {}
-    for m in re.finditer(r'traffic-record kernel="([^"]+)" fetch_bytes=(\d+) write_bytes=(\d+) '
-                         r'sources_sha256=([0-9a-f]+)', open(TRAFFIC_RECORD).read()):
-        rec[m.group(1)] = (int(m.group(2)), int(m.group(3)), m.group(4))
-    if not kernels or any(k not in rec for k in kernels):
-        return None
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
         h.update(open(os.path.join(ROOT, "paper_1402_5168_amd", "csrc", f), "rb").read())
-    if any(rec[k][2] != h.hexdigest() for k in kernels):
-        return None
-    n = len(kernels)
-    return {"read": sum(rec[k][0] for k in kernels) / n,
-            "written": sum(rec[k][1] for k in kernels) / n,
-            "per_launch": {k: {"read": rec[k][0], "written": rec[k][1]} for k in kernels}}
+    return h.hexdigest()
+
+
+def measured_step_traffic(tiles, variants) -> dict:
+    """HBM bytes of one step per kernel class of the default workload, from
+    the committed counter record: {class: {"read", "written", "launches"}},
+    only for records taken with these sources and with the plan's tuned
+    tiles and variants (empty otherwise)."""
+    import re
+
+    if not os.path.exists(TRAFFIC_RECORD):
+        return {}
+    want = (",".join(map(str, tiles)), ",".join(map(str, variants)))
+    out = {}
+    digest = None
+    for m in re.finditer(r'traffic-step class="([^"]+)" launches=(\d+) tiles=([0-9,]+) '
+                         r'variants=([0-9,]+) fetch_bytes=(\d+) write_bytes=(\d+) '
+                         r'sources_sha256=([0-9a-f]+)', open(TRAFFIC_RECORD).read()):
+        if (m.group(3), m.group(4)) != want:
+            continue
+        digest = digest or sources_digest()
+        if m.group(7) != digest:
+            continue
+        out[m.group(1)] = {"read": int(m.group(5)), "written": int(m.group(6)),
+                           "launches": int(m.group(2))}
+    return out
 
 
 def interface_nodes(mesh, walls: bool = False) -> int:
@@ -103,6 +113,125 @@ def algorithmic_bytes(mesh, npole: int, nrhs: int, sw: bool = False) -> dict:
     leaf_down = ncol * (q2 * E * c16 + E * c16 + 2 * mesh.n_el * q2 * c16)
     pole_sum = ncol * mesh.n_el * q2 * c16 + nrhs * 3 * mesh.n_el * q2 * d8
     return {"k_leaf_up": leaf_up, "k_leaf_down": leaf_down, "k_pole_sum": pole_sum}
+
+
+def merge_levels(mesh, walls: bool = False) -> list:
+    """Boxes of each merge level, from the elements up: (n1, n2, n3) per box.
+
+    Boxes are rectangles of elements; a level pairs neighbouring boxes along
+    x while the boxes are no wider than tall (or only one row of boxes is
+    left), else along y.  n3 counts the unknowns on the pair's shared edge,
+    n1 and n2 those on the rest of each child's boundary: interface nodes,
+    and wall nodes with slip walls (a Dirichlet boundary has none)."""
+    q = mesh.q
+
+    def ext(x0, y0, w, h):
+        n = 0
+        for length, outer in ((h, x0 == 0), (h, x0 + w == mesh.nex),
+                              (w, y0 == 0), (w, y0 + h == mesh.ney)):
+            if walls or not outer:
+                n += length * q
+        return n
+
+    nbx, nby = mesh.nex, mesh.ney
+    boxes = [(ex, ey, 1, 1) for ey in range(mesh.ney) for ex in range(mesh.nex)]
+    levels = []
+    while nbx * nby > 1:
+        w, h = boxes[0][2], boxes[0][3]
+        in_x = nbx > 1 and (w <= h or nby == 1)
+        nbx2, nby2 = (nbx // 2, nby) if in_x else (nbx, nby // 2)
+        nxt, lev = [], []
+        for by in range(nby2):
+            for bx in range(nbx2):
+                a = boxes[2 * bx + nbx * by] if in_x else boxes[bx + nbx * 2 * by]
+                b = boxes[2 * bx + 1 + nbx * by] if in_x else boxes[bx + nbx * (2 * by + 1)]
+                n3 = (a[3] if in_x else a[2]) * q
+                lev.append((ext(*a) - n3, ext(*b) - n3, n3))
+                nxt.append((a[0], a[1], a[2] * 2, a[3]) if in_x else (a[0], a[1], a[2], a[3] * 2))
+        levels.append(lev)
+        boxes, nbx, nby = nxt, nbx2, nby2
+    return levels
+
+
+def stage_work(mesh, npole: int, nrhs: int, fp32: bool) -> dict:
+    """Algorithmic HBM bytes and flops of one step of the batched wave
+    problem, per kernel class: (bytes, flops, flop peak in TFLOP/s).
+
+    Operators are read once per pole and serve all nrhs columns; vectors
+    are read and written once per column (pole x RHS); c bytes per complex
+    entry (8 FP32, 16 FP64).  The precision form runs two sweeps (the first
+    and the correction), the FP64 form one; per sweep:
+      k_leaf_up     W (q^4 per element and pole); w and h written
+                    (q^2 + e per element and column); first sweep: the
+                    FP64 sources (2 q^2 per element and RHS); correction:
+                    the FP32 interior residual g (q^2 per element and column)
+      k_merge_up    Y (ext x n3 per box and pole); children's h read
+                    (ext + 2 n3), g3 and the box's h written (n3 + ext);
+                    correction: the FP64 flux residual at both sides of
+                    each shared edge node (16 B, e per element and column)
+      k_merge_down  Z (n3 x (ext + n3)); u_ext and g3 read (ext + n3),
+                    the children's u written (ext + 2 n3)
+      k_leaf_down   S (q^2 x e per element and pole); u_e and w read; the
+                    first sweep writes y (q^2); the last reads y (precision
+                    form) and reads and writes the FP64 state (2 q^2 per
+                    element and RHS) for the pole sum and post-map
+      k_residual    (precision form) y and u_e read (FP32), the sources and
+                    c^2 read (FP64), the FP32 interior residual and the FP64
+                    flux values written; FP64 vector flops: 8 p per interior
+                    node and column, 4 p per edge node
+    Flops: 8 per complex multiply-add of the products."""
+    q2 = mesh.q * mesh.q
+    nel = mesh.n_el
+    E = interface_nodes(mesh)
+    ncol = npole * nrhs
+    c = 8 if fp32 else 16
+    sweeps = 2 if fp32 else 1
+    boxes = [b for lev in merge_levels(mesh) for b in lev]
+    Y = sum((n1 + n2) * n3 for n1, n2, n3 in boxes)
+    Z = sum(n3 * (n1 + n2 + n3) for n1, n2, n3 in boxes)
+    V = sum(2 * (n1 + n2) + 3 * n3 for n1, n2, n3 in boxes)
+    peak = FP32_PEAK_TFLOPS if fp32 else FP64_PEAK_TFLOPS
+    state = 2 * nel * q2 * 8 * nrhs           # the FP64 (u, v) of all RHS
+    leaf_up = sweeps * (c * npole * nel * q2 * q2 + c * ncol * (nel * q2 + E)) + state
+    merge_up = sweeps * (c * npole * Y + c * ncol * V)
+    merge_down = sweeps * (c * npole * Z + c * ncol * V)
+    leaf_down = sweeps * (c * npole * q2 * E + c * ncol * (E + nel * q2)) + 2 * state
+    out = {
+        "k_leaf_up": (leaf_up, 8.0 * sweeps * ncol * nel * q2 * q2, peak),
+        "k_merge_up": (merge_up, 8.0 * sweeps * ncol * Y, peak),
+        "k_merge_down": (merge_down, 8.0 * sweeps * ncol * Z, peak),
+    }
+    if fp32:
+        out["k_leaf_up"] = (leaf_up + 8 * ncol * nel * q2, *out["k_leaf_up"][1:])
+        out["k_merge_up"] = (merge_up + 16 * ncol * E, *out["k_merge_up"][1:])
+        leaf_down += 2 * 8 * ncol * nel * q2
+        p = mesh.p
+        res = 8 * ncol * (nel * q2 + E) + state + 8 * nel * p * p + 8 * ncol * nel * q2 \
+            + 16 * ncol * E
+        out["k_residual"] = (res, float(ncol * (8 * p * nel * q2 + 4 * p * E)),
+                             FP64_PEAK_TFLOPS)
+    out["k_leaf_down"] = (leaf_down, 8.0 * sweeps * ncol * q2 * E, peak)
+    return out
+
+
+def stage_rooflines(work: dict, ms_per_step: dict) -> dict:
+    """Each kernel class against its own roofline: the time its bytes take
+    at the HBM peak or its flops at the flop peak, whichever is longer,
+    over its measured time per step."""
+    out = {}
+    for name, (nbytes, flops, peak) in work.items():
+        ms = ms_per_step.get(name)
+        if not ms:
+            continue
+        t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+        t_flop = flops / (peak * 1e12)
+        out[name] = {"ms_per_step": ms, "bytes_per_step": nbytes, "flops_per_step": flops,
+                     "GBps": nbytes / (ms * 1e-3) / 1e9,
+                     "TFLOPs": flops / (ms * 1e-3) / 1e12,
+                     "bound": "hbm" if t_hbm >= t_flop else
+                              ("mfma" if name != "k_residual" else "alu"),
+                     "frac": max(t_hbm, t_flop) / (ms * 1e-3)}
+    return out
 
 
 def cpu_baseline_sw(recipe, npole_folded: int, sub: int = 8, poles: int = 4,
@@ -259,36 +388,55 @@ def run(w, precision: str, unbatched: bool, steps: int, warmup: int, profile: bo
                 entry["bytes_per_launch"] = ab[name]
                 entry["GBps"] = ab[name] / (avg * 1e-3) / 1e9
             kernels[name] = entry
-        dom = kernels["k_leaf_up"]
-        if batched:
-            # each stored entry serves nrhs columns: the sweeps are MFMA-bound
+        out["kernels"] = kernels
+        if batched and not sw:
+            # every kernel class against its roofline; the class with the
+            # most time per step is the roofline object
+            work = stage_work(m, info["folded_poles"], nrhs, fp32)
+            st = stage_rooflines(work, {k: v["ms_total"] / steps for k, v in kernels.items()})
+            meas = {}
+            if fp32 and w.recipe.name == "wave_64x64_p10" and nrhs == 32:
+                meas = measured_step_traffic(tiles, variants)
+            for name, e in st.items():
+                e["launches_per_step"] = kernels[name]["launches"] / steps
+                t = meas.get(name)
+                ok = t is not None and t["launches"] == e["launches_per_step"]
+                e["traffic"] = t["read"] + t["written"] if ok else None
+                e["traffic_split"] = {"read": t["read"], "written": t["written"]} if ok else None
+            dom = max(st, key=lambda k: st[k]["ms_per_step"])
+            d = st[dom]
+            n = d["launches_per_step"]
+            hbm = d["bound"] == "hbm"
+            achieved = d["GBps"] if hbm else d["TFLOPs"]
+            peak = HBM_PEAK_GBS if hbm else work[dom][2]
+            out["roofline"] = {
+                "bound": d["bound"], "kernel": dom, "launches_per_step": n,
+                "achieved": achieved, "peak": peak, "unit": "GB/s" if hbm else "TFLOP/s",
+                "frac": achieved / peak,
+                "algorithmic_per_launch": (d["bytes_per_step"] if hbm else d["flops_per_step"]) / n,
+                "ms_per_launch": d["ms_per_step"] / n,
+                "traffic": None if d["traffic"] is None else d["traffic"] / n,
+                "step_TFLOPs": info["flops_per_step"] / (ms_step * 1e-3) / 1e12}
+            out["stages"] = st
+        elif batched:
+            # shallow water: the element upward sweep on the matrix cores
+            dom = kernels["k_leaf_up"]
             flops = leaf_up_flops(m, info["folded_poles"], nrhs)
             tf = flops / (dom["ms_avg"] * 1e-3) / 1e12
             dom["flops_per_launch"] = flops
             dom["TFLOPs"] = tf
             peak = FP32_PEAK_TFLOPS if fp32 else FP64_PEAK_TFLOPS
-            tr = None
-            if fp32 and not sw and w.recipe.name == "wave_64x64_p10" and nrhs == 32:
-                # the step's two upward sweeps: the first (sources staged or
-                # not, as tuned) and the correction sweep (never staged)
-                # (the record holds the staged first sweep only: an unstaged
-                # first sweep shares its kernel name with the correction sweep)
-                nt, staged = tiles[0], variants[0]
-                if staged:
-                    tr = measured_traffic([f"hx::k_leaf_up_mm<float, {nt}, true>",
-                                           f"hx::k_leaf_up_mm<float, {nt}, false>"])
             out["roofline"] = {"bound": "mfma", "kernel": "k_leaf_up", "achieved": tf,
                                "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
-                               "traffic": None if tr is None else tr["read"] + tr["written"],
-                               "traffic_split": tr,
+                               "traffic": None,
                                "step_TFLOPs": info["flops_per_step"] / (ms_step * 1e-3) / 1e12}
         else:
+            dom = kernels["k_leaf_up"]
             out["roofline"] = {"bound": "hbm", "kernel": "k_leaf_up", "achieved": dom["GBps"],
                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": None,
                                "step_op_bytes_GBps":
                                    info["op_bytes_per_step"] / (ms_step * 1e-3) / 1e9}
-        out["kernels"] = kernels
     return out, final
 
 
@@ -418,6 +566,39 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def trace_step(db: str) -> None:
+    """The last step of a kernel trace of this benchmark: its dispatches
+    from the last upward element sweep that follows a downward one (the
+    step's first launch) to the end of the trace, with their durations,
+    and the sums per kernel class.  With --steps K the trace ends with the
+    per-kernel timing pass, whose steps launch the same kernels as the
+    timed graph replays."""
+    import sqlite3
+
+    rows = list(sqlite3.connect(db).execute(
+        "select name, start, end, grid_x, workgroup_x from kernels order by start"))
+    rows = [r for r in rows if "hx::k_" in r[0]]
+    starts = [i for i in range(1, len(rows))
+              if "k_leaf_up" in rows[i][0] and "k_leaf_down" in rows[i - 1][0]]
+    if not starts:
+        raise SystemExit("no complete step in the trace")
+    step = rows[starts[-1]:]
+    classes = {}
+    print("| # | kernel | blocks | us |\n|---:|---|---:|---:|")
+    for i, (name, t0, t1, gx, wx) in enumerate(step):
+        k = name.split("(")[0].replace("void ", "")
+        us = (t1 - t0) / 1e3
+        print(f"| {i} | {k} | {gx // max(wx, 1)} | {us:.1f} |")
+        cls = k.replace("hx::", "").split("<")[0].replace("_sum_mm", "").replace("_mm", "")
+        c = classes.setdefault(cls, [0, 0.0])
+        c[0] += 1
+        c[1] += us
+    print("\n| class | launches | ms per step | ms per launch |\n|---|---:|---:|---:|")
+    for cls, (n, us) in classes.items():
+        print(f"| {cls} | {n} | {us / 1e3:.3f} | {us / 1e3 / n:.3f} |")
+    print(f"\nstep: {len(step)} launches, {sum(c[1] for c in classes.values()) / 1e3:.3f} ms of kernels")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -442,7 +623,13 @@ def main():
                          "or use the default rule (0)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device once (calibrates HBM byte counters)")
+    ap.add_argument("--trace-step", metavar="DB", default=None,
+                    help="only print the last step's kernels from a rocprofv3 --kernel-trace "
+                         "database (launch order, durations, per-class sums)")
     args = ap.parse_args()
+    if args.trace_step:
+        trace_step(args.trace_step)
+        return
     if args.copy_probe:
         import torch
         x = torch.ones(2 ** 28, dtype=torch.float32, device="cuda:0")
@@ -498,6 +685,8 @@ def main():
         "roofline": head["roofline"],
         "kernels": head["kernels"],
     }
+    if "stages" in head:
+        out["stages"] = head["stages"]
     if not args.no_compare and args.precision == "fp32-refine":
         # the same inputs in FP64: batched, and one right-hand side
         ref, ref_final = run(w, "fp64", False, args.steps, args.warmup, profile=False,

@@ -1,9 +1,6 @@
 """Host-side checks of bench.py's bookkeeping (no GPU): the HBM-traffic
 record lookup and the algorithmic byte and flop counts it reports against.
 """
-import hashlib
-import os
-
 import pytest
 
 import bench
@@ -16,36 +13,127 @@ def _record(tmp_path, lines):
     return str(p)
 
 
-def _digest():
-    h = hashlib.sha256()
-    for f in bench.TRAFFIC_SOURCES:
-        h.update(open(os.path.join(bench.ROOT, "paper_1402_5168_amd", "csrc", f), "rb").read())
-    return h.hexdigest()
+def _step(cls, launches, tiles, variants, fetch, write, digest):
+    return (f'    traffic-step class="{cls}" launches={launches} tiles={tiles} '
+            f'variants={variants} fetch_bytes={fetch} write_bytes={write} sources_sha256={digest}')
 
 
-def test_traffic_record_is_the_mean_of_the_listed_kernels(tmp_path, monkeypatch):
-    d = _digest()
+def test_step_traffic_record_is_read_per_class(tmp_path, monkeypatch):
+    d = bench.sources_digest()
     monkeypatch.setattr(bench, "TRAFFIC_RECORD", _record(tmp_path, [
-        f'    traffic-record kernel="k<a>" fetch_bytes=100 write_bytes=10 sources_sha256={d}',
-        f'    traffic-record kernel="k<b>" fetch_bytes=300 write_bytes=30 sources_sha256={d}',
+        _step("k_merge_up", 24, "2,1,2,1,1", "1,0,0,0,0", 300, 30, d),
+        _step("k_leaf_up", 2, "2,1,2,1,1", "1,0,0,0,0", 100, 10, d),
     ]))
-    tr = bench.measured_traffic(["k<a>", "k<b>"])
-    assert tr["read"] == 200 and tr["written"] == 20
-    assert tr["per_launch"]["k<b>"] == {"read": 300, "written": 30}
+    tr = bench.measured_step_traffic([2, 1, 2, 1, 1], [1, 0, 0, 0, 0])
+    assert tr == {"k_merge_up": {"read": 300, "written": 30, "launches": 24},
+                  "k_leaf_up": {"read": 100, "written": 10, "launches": 2}}
 
 
-def test_traffic_record_is_void_for_other_sources_or_kernels(tmp_path, monkeypatch):
-    d = _digest()
+def test_step_traffic_record_is_void_for_other_sources_or_shapes(tmp_path, monkeypatch):
+    d = bench.sources_digest()
     monkeypatch.setattr(bench, "TRAFFIC_RECORD", _record(tmp_path, [
-        f'    traffic-record kernel="k<a>" fetch_bytes=100 write_bytes=10 sources_sha256={d}',
-        '    traffic-record kernel="k<b>" fetch_bytes=300 write_bytes=30 sources_sha256=' + "0" * 64,
+        _step("k_merge_up", 24, "2,1,2,1,1", "1,0,0,0,0", 300, 30, "0" * 64),
+        _step("k_leaf_up", 2, "2,1,2,1,1", "1,0,0,0,0", 100, 10, d),
     ]))
-    assert bench.measured_traffic(["k<a>"]) is not None
-    assert bench.measured_traffic(["k<b>"]) is None            # sources changed since
-    assert bench.measured_traffic(["k<a>", "k<c>"]) is None    # a kernel not recorded
-    assert bench.measured_traffic([]) is None
+    assert list(bench.measured_step_traffic([2, 1, 2, 1, 1], [1, 0, 0, 0, 0])) == ["k_leaf_up"]
+    assert bench.measured_step_traffic([1, 1, 2, 1, 1], [1, 0, 0, 0, 0]) == {}   # other tiles
+    assert bench.measured_step_traffic([2, 1, 2, 1, 1], [0, 0, 0, 0, 0]) == {}   # other variants
     monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(tmp_path / "missing.md"))
-    assert bench.measured_traffic(["k<a>"]) is None
+    assert bench.measured_step_traffic([2, 1, 2, 1, 1], [1, 0, 0, 0, 0]) == {}
+
+
+def test_committed_record_matches_these_sources():
+    """The committed counter record was taken with the current kernel and
+    plan sources (else the benchmark reports no traffic)."""
+    tr = bench.measured_step_traffic([2, 1, 2, 1, 1], [1, 0, 0, 0, 0])
+    assert set(tr) == {"k_leaf_up", "k_merge_up", "k_merge_down", "k_leaf_down", "k_residual"}
+
+
+def _tree_by_sets(nex, ney, q, walls):
+    """Merge tree from explicit node sets: every element side owns q node
+    ids (shared by the two elements of an interior side; on the outer
+    boundary only with walls); a merge's n3 is the intersection of its
+    children's sets, n1 and n2 the rest of each, the parent keeps the
+    symmetric difference."""
+    ids = {}
+
+    def side(key):
+        return ids.setdefault(key, [len(ids) * q + t for t in range(q)])
+
+    sets = []
+    for ey in range(ney):
+        for ex in range(nex):
+            s = set()
+            for key, outer in ((("v", ex, ey), ex == 0), (("v", ex + 1, ey), ex + 1 == nex),
+                               (("h", ex, ey), ey == 0), (("h", ex, ey + 1), ey + 1 == ney)):
+                if walls or not outer:
+                    s |= set(side(key))
+            sets.append(s)
+    nbx, nby, w, h = nex, ney, 1, 1
+    levels = []
+    while nbx * nby > 1:
+        in_x = nbx > 1 and (w <= h or nby == 1)
+        nbx2, nby2 = (nbx // 2, nby) if in_x else (nbx, nby // 2)
+        nxt, lev = [], []
+        for by in range(nby2):
+            for bx in range(nbx2):
+                a = sets[2 * bx + nbx * by] if in_x else sets[bx + nbx * 2 * by]
+                b = sets[2 * bx + 1 + nbx * by] if in_x else sets[bx + nbx * (2 * by + 1)]
+                lev.append((len(a - b), len(b - a), len(a & b)))
+                nxt.append(a ^ b)
+        levels.append(lev)
+        sets, nbx, nby = nxt, nbx2, nby2
+        w, h = (2 * w, h) if in_x else (w, 2 * h)
+    return levels
+
+
+@pytest.mark.parametrize("nex,ney,p,walls", [(2, 1, 4, False), (2, 2, 6, False), (4, 2, 8, False),
+                                             (4, 4, 10, False), (8, 4, 6, False), (4, 4, 6, True),
+                                             (8, 8, 5, True), (2, 4, 7, True)])
+def test_merge_levels_match_explicit_node_sets(nex, ney, p, walls):
+    m = layout.Mesh(nex, ney, p)
+    lv = bench.merge_levels(m, walls)
+    assert lv == _tree_by_sets(nex, ney, m.q, walls)
+    # every interface node is shared at exactly one merge; the root keeps
+    # only wall nodes
+    n3 = sum(b[2] for lev in lv for b in lev)
+    walls_nodes = 2 * (nex + ney) * m.q if walls else 0
+    assert 2 * n3 == bench.interface_nodes(m, walls) - walls_nodes
+    assert lv[-1] == [(lv[-1][0][0], lv[-1][0][1], lv[-1][0][2])]
+    assert lv[-1][0][0] + lv[-1][0][1] == walls_nodes
+
+
+def test_stage_work_by_hand():
+    """Two elements of p = 4 (2 x 2 interior nodes, one shared edge of 2
+    nodes), one pole, one RHS, FP64 (16 B per complex), one sweep.
+    Element up: W 2 x 16 entries, w 2 x 4 and h 4 entries written, the
+    (u, v) state (2 x 2 x 4 doubles) read.  The one merge: Y is empty
+    (no exterior), Z is 2 x 2, vectors 2 ext + 3 n3 = 6 rows.  Element
+    down: S 4 x 4 (interior x edge slots, summed over both), u_e (4) and
+    w (8) read, state read and written."""
+    m = layout.Mesh(2, 1, 4)
+    w = bench.stage_work(m, 1, 1, False)
+    assert w["k_leaf_up"][:2] == (16 * 32 + 16 * 12 + 128, 8.0 * 32)
+    assert w["k_merge_up"][:2] == (16 * 6, 0.0)
+    assert w["k_merge_down"][:2] == (16 * 4 + 16 * 6, 8.0 * 4)
+    assert w["k_leaf_down"][:2] == (16 * 16 + 16 * 12 + 2 * 128, 8.0 * 16)
+    assert "k_residual" not in w
+    w32 = bench.stage_work(m, 1, 1, True)   # two sweeps, 8 B per complex
+    assert w32["k_merge_down"][:2] == (2 * (8 * 4 + 8 * 6), 2 * 8.0 * 4)
+    # correction sweep: the FP64 flux residual of the 4 edge slots
+    assert w32["k_merge_up"][0] == 2 * 8 * 6 + 16 * 4
+
+
+def test_stage_rooflines_take_the_longer_bound():
+    work = {"k_leaf_up": (8e9, 1e12, 100.0),      # 1 ms of bytes, 10 ms of flops
+            "k_merge_up": (16e9, 1e9, 100.0),     # 2 ms of bytes
+            "k_residual": (1e6, 1e12, 78.6)}
+    st = bench.stage_rooflines(work, {"k_leaf_up": 20.0, "k_merge_up": 4.0, "k_residual": 50.0})
+    assert st["k_leaf_up"]["bound"] == "mfma" and st["k_leaf_up"]["frac"] == pytest.approx(0.5)
+    assert st["k_merge_up"]["bound"] == "hbm" and st["k_merge_up"]["frac"] == pytest.approx(0.5)
+    assert st["k_merge_up"]["GBps"] == pytest.approx(4000.0)
+    assert st["k_residual"]["bound"] == "alu"
+    assert "k_leaf_down" not in bench.stage_rooflines(work, {"k_leaf_down": 1.0})
 
 
 @pytest.mark.parametrize("nex,ney,p,walls", [(1, 1, 8, False), (2, 1, 6, False), (4, 4, 10, False),
