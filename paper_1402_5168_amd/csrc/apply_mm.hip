@@ -264,6 +264,12 @@ __device__ __forceinline__ void mm_emit(const Acc<T, NT>& acc, int row0, int nro
 
 constexpr int kKC = 64;  // k-chunk of B staged in LDS
 
+// k-chunk of the four-wave merge blocks: 128 columns of FP32 B (17 or 34 KiB
+// of LDS), so that a wave's operator ring drains at a chunk end half as
+// often; 64 of FP64 (the static LDS limit); one-wave blocks take 32.
+template <class T, int WV>
+constexpr int merge_kc() { return WV == 4 ? (sizeof(T) == 4 ? 2 * kKC : kKC) : 32; }
+
 // ---- leaf upward: g from the sources, w = W g, h = N_i w -------------------------
 // block = (leaf, rhs tile, group of pole_group poles); it stages the source
 // fields of its element and right-hand sides once in LDS, then walks its
@@ -415,7 +421,7 @@ template <class T, int NT, int WV>
 __device__ __forceinline__ void merge_up_body(const MmMergeArgs<T>& a, const int bid) {
   using C = typename MM<T>::C;
   constexpr int RT = 16 * NT, BST = RT + 1;
-  constexpr int RB = 16 * WV, KC = WV == 4 ? kKC : 32;  // rows per block, k-chunk
+  constexpr int RB = 16 * WV, KC = merge_kc<T, WV>();  // rows per block, k-chunk
   __shared__ C Bs[KC * BST];
   const int n_rt = (a.nrhs + RT - 1) / RT;
   const int G = a.pole_group, npg = (a.npole + G - 1) / G;
@@ -532,7 +538,7 @@ template <class T, int NT, int WV>
 __device__ __forceinline__ void merge_down_body(const MmMergeArgs<T>& a, const int bid) {
   using C = typename MM<T>::C;
   constexpr int RT = 16 * NT, BST = RT + 1;
-  constexpr int RB = 16 * WV, KC = WV == 4 ? kKC : 32;  // rows per block, k-chunk
+  constexpr int RB = 16 * WV, KC = merge_kc<T, WV>();  // rows per block, k-chunk
   __shared__ C Bs[KC * BST];
   const int n_rt = (a.nrhs + RT - 1) / RT;
   int rest = bid;
