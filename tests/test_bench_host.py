@@ -156,3 +156,38 @@ def test_leaf_up_flops_counts_complex_products():
     """8 real flops per complex multiply-add, q^4 per element and column."""
     m = layout.Mesh(4, 2, 10)
     assert bench.leaf_up_flops(m, 66, 32) == 8.0 * 8 * 64 * 64 * 66 * 32
+
+
+def test_trace_step_lists_the_last_step(tmp_path, capsys):
+    """A kernel trace of two steps (element up, merge up x2, merge down x2,
+    element down) plus a foreign kernel: the last step alone is listed and
+    summed per class."""
+    import sqlite3
+
+    db = tmp_path / "trace.db"
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, start int, end int, grid_x int, workgroup_x int)")
+    step = [("void hx::k_leaf_up_mm<float, 2, true>(args)", 1000),
+            ("void hx::k_merge_up_mm<float, 1, 4>(args)", 300),
+            ("void hx::k_merge_up_mm<float, 1, 1>(args)", 100),
+            ("void hx::k_merge_down_mm<float, 1, 4>(args)", 200),
+            ("void hx::k_merge_down_mm<float, 1, 1>(args)", 200),
+            ("void hx::k_leaf_down_sum_mm<float, 1>(args)", 500)]
+    t = 0
+    for rep in range(2):
+        for name, dur in step:
+            scale = 1 + rep          # the second step takes twice as long
+            con.execute("insert into kernels values (?, ?, ?, ?, ?)",
+                        (name, t, t + dur * scale * 1000, 256 * 64, 256))
+            t += dur * scale * 1000 + 10
+        con.execute("insert into kernels values ('copyBuffer', ?, ?, 1, 1)", (t, t + 5))
+        t += 10
+    con.commit()
+    con.close()
+    bench.trace_step(str(db))
+    out = capsys.readouterr().out
+    assert "| k_merge_up | 2 | 0.800 | 0.400 |" in out
+    assert "| k_merge_down | 2 | 0.800 | 0.400 |" in out
+    assert "| k_leaf_up | 1 | 2.000 | 2.000 |" in out
+    assert "| k_leaf_down | 1 | 1.000 | 1.000 |" in out
+    assert "step: 6 launches, 4.600 ms of kernels" in out
