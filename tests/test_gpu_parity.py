@@ -227,6 +227,36 @@ def test_precision_form_matches_oracle(nex, ney, p, nrhs, steps):
     check(w, got, steps, tol=TOL32)
 
 
+@pytest.fixture(scope="module")
+def wave_16x16_p10():
+    """16x16 elements, p = 10, 17 RHS with nonzero velocities, and the
+    oracle's state after 2 steps (shared by both precisions)."""
+    w = make(16, 16, 10, n_rhs=17)
+    rng = np.random.default_rng(11)
+    w.v0 = 0.2 * rng.standard_normal(w.u0.shape) * w.u0
+    say("oracle: 16x16 p=10, 17 RHS, 2 steps")
+    return w, oracle_run(w, 2)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_merges_with_several_chunks_and_row_groups(wave_16x16_p10, precision):
+    """The upper merges of a 16x16 mesh (p = 10) have exteriors of 128-160
+    rows and interfaces of 64-128 nodes: the matrix-core upward blocks run
+    several row groups, the downward ones several row groups (128-row top
+    interface) and several staged k-chunks (ext + n3 = 192 columns: two
+    chunks of 128 in FP32, three of 64 in FP64), and the two-tile RHS blocks
+    end ragged (17 of 32 columns)."""
+    w, ref = wave_16x16_p10
+    say(f"batched 16x16 p=10 nrhs=17, precision {precision}, 2 steps")
+    got = gpu_run([w], 2, precision=precision)[0]
+    tol = TOL if precision == 0 else TOL32
+    worst = 0.0
+    for r, (u, v) in enumerate(ref):
+        worst = max(worst, rel_err(got[r, 0], u), rel_err(got[r, 1], v))
+    say(f"max rel err {worst:.3e} (tol {tol:.0e})")
+    assert worst <= tol
+
+
 def test_precision_form_wave_4x4_p12_100_steps():
     say("fp32+refine wave_4x4_p12, 100 steps")
     w = configs.make(configs.scaled("wave_4x4_p12", 4, 4, n_steps=100))
