@@ -449,6 +449,22 @@ __device__ __forceinline__ void merge_up_body(const MmMergeArgs<T>& a, const int
     const int row = row0 + MM<T>::row(lane, v);
     bo[v] = row >= ext ? 0 : row < n1 ? B.a_vec + i1[row] : B.b_vec + i2[row - n1];
   }
+  // the interface rows' child positions (and flux slots), the same for every
+  // pole, held in LDS so that the staging's gathers wait on one LDS read
+  constexpr int kIdxLds = 256;
+  __shared__ int sidx[4 * kIdxLds];
+  const bool sl = n3 <= kIdxLds;
+  if (sl) {
+    for (int t = threadIdx.x; t < n3; t += blockDim.x) {
+      sidx[t] = i3a[t];
+      sidx[kIdxLds + t] = i3b[t];
+      if (a.dn) {
+        sidx[2 * kIdxLds + t] = ja[t];
+        sidx[3 * kIdxLds + t] = ja[n3 + t];
+      }
+    }
+    __syncthreads();
+  }
   const int p_end = min(a.npole, (pg + 1) * G);
   for (int pole = pg * G; pole < p_end; ++pole) {
     const C* hc = a.child + (long long)pole * a.child_pole * r;
@@ -479,16 +495,20 @@ __device__ __forceinline__ void merge_up_body(const MmMergeArgs<T>& a, const int
         C v;
         v.x = v.y = T(0);
         if (k < kc && rhs < r) {
-          const C x = hc[(long long)(B.a_vec + i3a[k0 + k]) * r + rhs];
-          const C y = hc[(long long)(B.b_vec + i3b[k0 + k]) * r + rhs];
+          const int kg = k0 + k;
+          const int ia = sl ? sidx[kg] : i3a[kg], ib = sl ? sidx[kIdxLds + kg] : i3b[kg];
+          const C x = hc[(long long)(B.a_vec + ia) * r + rhs];
+          const C y = hc[(long long)(B.b_vec + ib) * r + rhs];
           v.x = x.x + y.x;
           v.y = x.y + y.y;
           if (a.dn) {
             // flux rows of the correction: du/dn(a) + du/dn(b) = -(dn_a + dn_b),
             // which enters as g3 = h3a + h3b + dn_a + dn_b
             const double2* dp = a.dn + (long long)pole * a.dn_pole * r;
-            const double2 da = dp[(long long)ja[k0 + k] * r + rhs];
-            const double2 db = dp[(long long)ja[n3 + k0 + k] * r + rhs];
+            const int sa = sl ? sidx[2 * kIdxLds + kg] : ja[kg];
+            const int sb = sl ? sidx[3 * kIdxLds + kg] : ja[n3 + kg];
+            const double2 da = dp[(long long)sa * r + rhs];
+            const double2 db = dp[(long long)sb * r + rhs];
             v.x += T(da.x + db.x);
             v.y += T(da.y + db.y);
           }
