@@ -1,6 +1,7 @@
 """Host-side checks of bench.py's bookkeeping (no GPU): the HBM-traffic
 record lookup and the algorithmic byte and flop counts it reports against.
 """
+import numpy as np
 import pytest
 
 import bench
@@ -191,3 +192,40 @@ def test_trace_step_lists_the_last_step(tmp_path, capsys):
     assert "| k_leaf_up | 1 | 2.000 | 2.000 |" in out
     assert "| k_leaf_down | 1 | 1.000 | 1.000 |" in out
     assert "step: 6 launches, 4.600 ms of kernels" in out
+
+
+@pytest.mark.parametrize("nex,ney,walls", [(1, 1, False), (2, 1, False), (4, 4, False),
+                                           (16, 8, False), (2, 8, False), (4, 2, True),
+                                           (8, 8, True)])
+def test_library_operator_storage_equals_tree_counts(nex, ney, walls):
+    """The library's stored operator entries per pole (its plan query, no
+    GPU) equal the counts the benchmark derives from the mesh: W (q^4) and
+    S (q^2 e) per element, Y (ext n3) and Z (n3 (ext + n3)) per merge box,
+    and with slip walls the root's dense wall system (n_wall^2).  p = 10
+    (q = 8) keeps every block a multiple of the library's 8-entry
+    alignment, so the counts agree exactly."""
+    from paper_1402_5168_amd import hpsexp as hx
+    from workloads.rational import calibrated_fit
+
+    m = layout.Mesh(nex, ney, 10)
+    fit = calibrated_fit(21)
+    plan = hx.Plan()
+    nrhs = 3
+    if walls:
+        plan.add_sw(nex, ney, m.p, 1.0, 1.0, 0.5, 1e-10, fit.alpha, fit.b, nrhs=nrhs)
+    else:
+        plan.add(nex, ney, m.p, np.ones(m.n_el * m.p * m.p), 0.5, 1e-10, fit.alpha, fit.b,
+                 nrhs=nrhs)
+    info = plan.query()
+    plan.close()
+    q2 = m.q * m.q
+    boxes = [b for lev in bench.merge_levels(m, walls) for b in lev]
+    entries = (m.n_el * q2 * q2 + q2 * bench.interface_nodes(m, walls)
+               + sum((n1 + n2) * n3 + n3 * (n1 + n2 + n3) for n1, n2, n3 in boxes))
+    if walls:
+        entries += (2 * (nex + ney) * m.q) ** 2
+    npole = info["folded_poles"]
+    assert info["operator_bytes"] == 16 * npole * entries
+    if not walls:
+        # one batched FP64 sweep: 8 flops per stored entry and column
+        assert info["flops_per_step"] == 8.0 * npole * nrhs * entries
